@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the tent-pitched Trefftz-DG layer solve on one MI355X.
+
+One step = one pass of the whole hot path over the workload: restore the
+initial values and the flat front (device to device), then solve every layer
+of tents from t = 0 to T (one launch per layer; all tents of a layer in that
+launch).  Inputs (mesh tables, initial values, boundary data) are resident in
+HBM before the timed region starts.
+
+value = DOF-updates per second = sum over tents of dim U^p / wall time of a step.
+The roofline object reports the tent kernel: algorithmic FP64 flops per launch
+(the operation count of the method, not the kernel's padded work) divided by
+its average launch duration, measured with HIP events on the launch stream
+around every launch in the timed region.
+
+cpu_baseline: the CPU oracle (plain NumPy, one process) on a bounded prefix of
+the same workload, on this machine's host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tent DOF-updates/sec at fixed L2 error (FP64 plain vs mixed+learned-p); % matrix peak"
+FP64_PEAK = 78.6e12   # MI355X FP64 (vector and matrix), FLOP/s
+HBM_PEAK = 8.0e12     # B/s
+
+
+def workload(name):
+    from workloads import configs as C
+
+    if name == "cfg2":
+        pr = C.cfg2_plane_2d()
+        desc = ("2+1D plain FP64 batched: unit square, seeded Delaunay of a jittered 32x32 grid "
+                f"({len(pr.elems)} triangles, h~0.05), c=1, p=4 (25 basis functions), plane wave |k|=2pi, T=1")
+    elif name == "cfg1":
+        pr = C.cfg1_standing_1d()
+        desc = "1+1D plain: [0,1], 16 elements, c=1, p=3, standing wave, T=1"
+    elif name.startswith("cfg3"):
+        p = int(name.split("p")[-1]) if "p" in name else 8
+        pr = C.cfg3_precision_2d(p=p)
+        desc = f"2+1D: seeded Delaunay of a jittered 100x100 grid ({len(pr.elems)} triangles), c=1, p={p}, plane wave, T=1"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return pr, desc
+
+
+def op_counts(ctx, pr, tents):
+    """Algorithmic flops and HBM bytes per tent (point-value layout):
+    flops = 2*(2 Q_T nnz) [fields at top and bottom points] + K NW (NW+1) [symmetric Gram]
+          + 4 K NW [right-hand side and top evaluation] + 2/3 NW^3 + 2 NW^2 [LU and solve],
+    K = Q_T (n+1), Q_T = patch size * points per element; bytes = 2 Q_T (n+2) 8."""
+    info = ctx.table_info(pr.p)
+    NW = info["N"] - 1
+    n = pr.n
+    patch = np.bincount(pr.elems.ravel(), minlength=len(pr.coords))
+    QT = patch[tents.vertex].astype(np.float64) * info["Q"]
+    K = QT * (n + 1)
+    flops = 4.0 * QT * info["nnz_fields"] + K * NW * (NW + 1) + 4.0 * K * NW + (2.0 / 3.0) * NW ** 3 + 2.0 * NW ** 2
+    bytes_ = 2.0 * QT * (n + 2) * 8
+    return flops, bytes_, info["N"]
+
+
+def cpu_baseline(pr, budget_s: float):
+    from oracle.pitcher import pitch
+    from oracle.tdg import OracleTDG
+    from oracle.trefftz import dim_U
+
+    f = pr.data
+    tents, lp = pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    o = OracleTDG(pr.coords, pr.elems, pr.c, tents, lp, p=pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta,
+                  gD=lambda x, t: f.v(x, t))
+    X = o.quad_points()
+    o.set_initial(f.v(X, 0.0), f.sigma(X, 0.0), f.U(X, 0.0))
+    t0 = time.perf_counter()
+    layers = 0
+    while layers < len(lp) - 1 and time.perf_counter() - t0 < budget_s:
+        o.run_layers(layers, layers + 1)
+        layers += 1
+    el = time.perf_counter() - t0
+    ntents = lp[layers]
+    dofs = ntents * dim_U(pr.n, pr.p)
+    return {"value": dofs / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {layers} of {len(lp) - 1} layers ({ntents} tents) in {el:.1f} s, one Python/NumPy "
+                      f"process (FP64, LAPACK LU)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
+              "DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1907_02367_amd import tdg
+
+    torch.cuda.set_device(0)
+    pr, desc = workload(args.workload)
+    f = pr.data
+    tents = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, tents, p_max=pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta)
+    xq, _ = ctx.quad_points()
+    ctx.set_initial(f.v(xq, 0.0), f.sigma(xq, 0.0), f.U(xq, 0.0))
+    if ctx.nb:
+        bx = ctx.boundary_points()
+        ctx.set_boundary(f.v(bx[:, :-1], bx[:, -1]))
+    flops, bytes_, N = op_counts(ctx, pr, tents)
+    L = tents.n_layers
+    lp = tents.layer_ptr
+    layer_flops = np.array([flops[lp[l]:lp[l + 1]].sum() for l in range(L)])
+    stream = torch.cuda.current_stream()
+    sptr = stream.cuda_stream
+
+    def step(events=None):
+        ctx.reset(sptr)
+        for l in range(L):
+            if events is not None:
+                events[l][0].record(stream)
+            ctx.layer_solve(l, l + 1, stream=sptr)
+            if events is not None:
+                events[l][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(L)]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.status()
+    ms_per_step = 1e3 * wall / args.steps
+    kern_ms = np.array([[ev[s][l][0].elapsed_time(ev[s][l][1]) for l in range(L)] for s in range(args.steps)])
+    avg_launch_s = kern_ms.mean() * 1e-3
+    flops_per_launch = layer_flops.mean()
+    achieved = flops_per_launch / avg_launch_s
+    e_abs, e_rel = ctx.eval_error(f.v(xq, pr.T), f.sigma(xq, pr.T))
+    dofs = float(tents.n_tents * N)
+    out = {
+        "metric": METRIC,
+        "value": dofs / (wall / args.steps),
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "tents": int(tents.n_tents), "layers": int(L), "dofs_per_tent": int(N),
+            "dof_updates_per_step": dofs, "e_abs_at_T": e_abs, "e_rel_at_T": e_rel,
+            "kernel_ms_per_step": float(kern_ms.sum(axis=1).mean()),
+            "parallelism": "single GPU, all tents of a layer in one launch",
+        },
+        "roofline": {
+            "bound": "alu", "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK, "traffic": None,
+            "kernel": f"tent_layer_kernel<{pr.n}>", "launches_per_step": int(L),
+            "avg_launch_us": avg_launch_s * 1e6, "alg_flops_per_launch": float(flops_per_launch),
+            "alg_bytes_per_launch": float(bytes_.sum() / L),
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * libtdg: tent-pitched space-time Trefftz-DG for the first-order acoustic
+ * wave system on MI355X (gfx950).
+ *
+ * The problem statement follows Sec. 2.1 of Perugia, Schoeberl, Stocker,
+ * Wintersteiger, "Tent pitching and Trefftz-DG method for the acoustic wave
+ * equation" (eq. 2.1):
+ *     div sigma + c^-2 dv/dt = 0,   grad v + dsigma/dt = 0   in Omega x (0,T),
+ *     v(.,0) = v0, sigma(.,0) = sigma0,  v = g_D on the (Dirichlet) boundary,
+ * with a wave speed c > 0 that is constant on each spatial element.  With
+ * v = dU/dt and sigma = -grad U this is the scalar wave equation (eq. 2.2).
+ *
+ * The library pitches tents over the vertex patches of a simplicial mesh of
+ * Omega (Sec. 2.2), then solves the tents layer by layer: all tents of a
+ * layer are independent and run in one launch.  Each tent solves the dense
+ * local Trefftz-DG system of eq. 4.1 (plus the interface terms of Sec. 4.2
+ * where the speed jumps inside the tent, and one recovery row per speed group
+ * for the constant of U, Sec. 5) and overwrites the values stored at the
+ * spatial quadrature points under it with its top values (Sec. 4.1).
+ *
+ * Conventions
+ *  - Degree p is the degree of the scalar Trefftz space U^p (Sec. 3); a tent
+ *    with one speed has N = dim U^p = C(p+n,n) + C(p-1+n,n) unknowns; the
+ *    first-order fields (v, sigma) have degree p - 1.
+ *  - Every call returns 0 (TDG_OK) or a negative TDG_E* code; no exception
+ *    crosses the interface.  tdg_last_error() gives a message for the
+ *    calling thread.
+ *  - Host arrays passed in are borrowed for the duration of the call and
+ *    copied.  tdg_tents and tdg_ctx are owned by the library and released by
+ *    tent_free / trefftz_destroy.
+ *  - The library allocates no device memory: the caller allocates the
+ *    buffers listed by trefftz_buffer_sizes (for instance as PyTorch tensors)
+ *    and hands them over with trefftz_bind; they must outlive the context.
+ *  - Device work is queued on the HIP stream passed in (NULL = the default
+ *    stream) and is asynchronous, except in calls that return host scalars,
+ *    which synchronise that stream.
+ *  - Double precision throughout unless the context is created with
+ *    precision = 1 (FP32 matrix-core assembly, FP64 solve and refinement).
+ */
+#ifndef TDG_H
+#define TDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TDG_OK = 0,
+  TDG_EINVAL = -1,      /* invalid argument (sizes, degenerate element, c <= 0, p out of range) */
+  TDG_ENONCAUSAL = -2,  /* a pitched front would not be space-like: c |grad phi| >= 1 (Sec. 2.2) */
+  TDG_ESINGULAR = -3,   /* a local system had a zero pivot */
+  TDG_ENOCONV = -4,     /* iterative refinement of the mixed-precision solve did not converge */
+  TDG_ENAN = -5,        /* NaN or Inf in data or results */
+  TDG_EHIP = -6,        /* a HIP runtime call failed */
+  TDG_ENOMEM = -7,      /* host allocation failed or a bound buffer is too small */
+  TDG_ESTATE = -8       /* call out of order (e.g. solve before bind) */
+};
+
+/* Spatial simplicial mesh.  coords: nv*dim doubles, vertex-major.
+ * elems: ne*(dim+1) vertex indices, element-major.  bface_kind must be NULL:
+ * every boundary facet is Dirichlet (the only kind the path supports). */
+typedef struct {
+  int32_t dim, nv, ne;
+  const double* coords;
+  const int32_t* elems;
+  const int8_t* bface_kind;
+} tdg_mesh;
+
+typedef struct tdg_tents tdg_tents;
+typedef struct tdg_ctx tdg_ctx;
+typedef void* tdg_stream; /* a hipStream_t */
+
+/* ---- tent pitching (host only, Sec. 2.2) -------------------------------------
+ * Advancing front from t = 0 to T.  Edge limit kappa_VW = gamma |X_W - X_V| /
+ * c_VW with c_VW the largest speed on the edge.  Each layer takes the local
+ * minima of the front in (tau, vertex) order, greedily skipping neighbours of
+ * vertices already taken, and raises each to min(T, min_W tau_W + kappa_VW).
+ * Fails with TDG_ENONCAUSAL if a front element would become c|grad phi| >= 1.
+ * c: ne speeds.  Requires dim in {1,2,3}, T > 0, gamma > 0. */
+int tent_pitch(const tdg_mesh* mesh, const double* c, double T, double gamma, tdg_tents** out);
+/* Layer and tent counts and the largest c|grad phi| over all pitched fronts. */
+int tent_info(const tdg_tents* tents, int32_t* n_layers, int64_t* n_tents, double* max_face_slope);
+/* Copies the tent list: vertex[n_tents], t_bot[n_tents], t_top[n_tents] and
+ * layer_ptr[n_layers+1] (tents of layer l are layer_ptr[l] .. layer_ptr[l+1]-1).
+ * Any pointer may be NULL to skip it. */
+int tent_export(const tdg_tents* tents, int32_t* vertex, double* t_bot, double* t_top, int64_t* layer_ptr);
+void tent_free(tdg_tents* tents);
+
+/* ---- solver context ------------------------------------------------------------ */
+typedef struct {
+  int32_t p_max;     /* highest degree of U^p used by any tent, 1..10 */
+  int32_t q;         /* Gauss points per direction of the simplex rule; 0 -> p_max (exact to 2q-1) */
+  double alpha;      /* penalty on Dirichlet and interface faces (Sec. 2.4), e.g. 0.5 */
+  double beta;       /* interface penalty (Sec. 2.4), e.g. 0.5 */
+  int32_t precision; /* 0 = FP64; 1 = FP32 matrix-core Gram + FP64 LU + FP64 refinement */
+  int32_t layout;    /* must be 1: values stored at spatial quadrature points (Sec. 4.1) */
+  int32_t recover_U; /* 1: one mean-matching row per speed group recovers U (Sec. 5); 0: off */
+} tdg_opts;
+
+enum {
+  TDG_BUF_F64 = 0,   /* static mesh/quadrature/basis tables, doubles */
+  TDG_BUF_I32 = 1,   /* static topology and tent tables, 32-bit ints */
+  TDG_BUF_STATE = 2, /* (v, sigma_1..sigma_n, U) at every quadrature point */
+  TDG_BUF_STATE0 = 3,/* copy of the initial values (trefftz_reset) */
+  TDG_BUF_TAU = 4,   /* advancing front, one time per vertex */
+  TDG_BUF_GD = 5,    /* Dirichlet data at the boundary points */
+  TDG_BUF_WORK = 6,  /* scratch: reductions, error data, device status word */
+  TDG_BUF_TENT = 7,  /* per-tent outputs: dissipation, refinement steps */
+  TDG_NBUF = 8
+};
+
+/* Builds the context for a pitched mesh: topology, the simplex rule and the
+ * exact Trefftz tables for p = 1..p_max.  c: ne speeds (the same as pitched). */
+int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents, const tdg_opts* opts,
+                   tdg_ctx** out);
+/* Spatial quadrature points, element-major: nq = ne * Q points of dim
+ * coordinates.  Pass xq = NULL to query nq.  w (nullable) gets the weights. */
+int trefftz_quad_points(const tdg_ctx* ctx, int64_t* nq, double* xq, double* w);
+/* Space-time points (dim+1 coordinates, time last) of every Dirichlet face of
+ * every tent, in tent order; the caller evaluates g_D there.  xt may be NULL. */
+int trefftz_boundary_points(const tdg_ctx* ctx, int64_t* nb, double* xt);
+/* Sizes in bytes of the TDG_NBUF device buffers the caller must provide. */
+int trefftz_buffer_sizes(const tdg_ctx* ctx, int64_t sizes[TDG_NBUF]);
+/* Hands over the device buffers (each at least the queried size, 256-byte
+ * aligned) and uploads the static tables on the stream. */
+int trefftz_bind(tdg_ctx* ctx, void* const dev_ptrs[TDG_NBUF], tdg_stream stream);
+/* Initial data at the quadrature points (host arrays): v0[nq], sigma0[nq*dim]
+ * (point-major), U0[nq] (nullable = 0).  Also resets the front to t = 0. */
+int trefftz_set_initial(tdg_ctx* ctx, const double* v0, const double* sigma0, const double* U0,
+                        tdg_stream stream);
+/* g_D at the boundary points of trefftz_boundary_points (host array, nb). */
+int trefftz_set_boundary(tdg_ctx* ctx, const double* gD, tdg_stream stream);
+/* Restores the initial values and the flat front t = 0 (device-to-device). */
+int trefftz_reset(tdg_ctx* ctx, tdg_stream stream);
+/* Solves the tents of layers [layer_begin, layer_end) in order, one launch
+ * per layer.  p_per_tent: device array of n_tents degrees (int8, 1..p_max) or
+ * NULL for p_max everywhere. */
+int trefftz_layer_solve(tdg_ctx* ctx, int32_t layer_begin, int32_t layer_end, const int8_t* p_per_tent,
+                        tdg_stream stream);
+/* Error e of Sec. 6 on the flat front t = T against host arrays of exact
+ * values at the quadrature points: v_ex[nq], sigma_ex[nq*dim].  e_rel divides
+ * by the same norm of the exact values.  Synchronises; also reports device
+ * errors raised by earlier solves. */
+int trefftz_eval_error(tdg_ctx* ctx, const double* v_ex, const double* sigma_ex, double* e_abs, double* e_rel,
+                       tdg_stream stream);
+/* Energy on the current front, E = 1/2 int c^-2 v^2 + |sigma|^2 - 2 v sigma.grad phi
+ * (the energy of Sec. 6.5 where the front is flat), and the summed per-tent
+ * dissipation of the tents solved since the last reset.  Synchronises. */
+int trefftz_energy(tdg_ctx* ctx, double* E_front, double* dissipated, tdg_stream stream);
+/* Synchronises the stream and returns the first error a kernel reported. */
+int trefftz_status(tdg_ctx* ctx, tdg_stream stream);
+/* Copies the stored values to host memory in the layout of the inputs:
+ * v[nq], sigma[nq*dim], U[nq] (any may be NULL).  Synchronises. */
+int trefftz_read_state(tdg_ctx* ctx, double* v, double* sigma, double* U, tdg_stream stream);
+/* Sizes of the degree-p basis tables: N = dim U^p, nnz_fields = stored
+ * coefficients of the first-order fields (v, sigma) of functions 1..N-1,
+ * n_mono = monomials t^k x^alpha with k + |alpha| <= p, and the points per
+ * element Q.  For operation counts; any output pointer may be NULL. */
+int trefftz_table_info(const tdg_ctx* ctx, int32_t p, int32_t* N, int32_t* nnz_fields, int32_t* n_mono, int32_t* Q);
+void trefftz_destroy(tdg_ctx* ctx);
+const char* tdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDG_H */

@@ -54,6 +54,10 @@ class Topology:
 
     def boundary_facets_at(self, V):
         """Boundary facets containing V: list of (element, opposite local index)."""
+        if not hasattr(self, "_bf"):
+            self._bf = {}
+        if V in self._bf:
+            return self._bf[V]
         out = []
         for e in self.patch[V]:
             vs = self.elems[e]
@@ -63,11 +67,16 @@ class Topology:
                 f = tuple(sorted(int(v) for j, v in enumerate(vs) if j != k))
                 if len(self.facets[f]) == 1:
                     out.append((e, k))
+        self._bf[V] = out
         return out
 
     def interface_facets_at(self, V):
         """Interior facets containing V whose two elements have different c:
         list of (e1, k1, e2, k2) with e1 < e2."""
+        if not hasattr(self, "_if"):
+            self._if = {}
+        if V in self._if:
+            return self._if[V]
         out = []
         for e in self.patch[V]:
             vs = self.elems[e]
@@ -81,7 +90,8 @@ class Topology:
                     if ea == e and self.c[ea] != self.c[eb]:
                         out.append((ea, ka, eb, kb) if ea < eb else (eb, kb, ea, ka))
         # each shared facet is found from both sides; keep one copy
-        return sorted(set(out))
+        self._if[V] = sorted(set(out))
+        return self._if[V]
 
     def outward_normal(self, e, k):
         """Unit outward normal of element e on the facet opposite local vertex k."""

@@ -1,0 +1,589 @@
+// C-ABI of libtdg: tent pitching, solver context, buffers, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+
+#include "tdg_internal.h"
+
+namespace tdg {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+}  // namespace tdg
+
+using namespace tdg;
+
+#define TDG_TRY_BEGIN try {
+#define TDG_TRY_END                      \
+  }                                      \
+  catch (const std::bad_alloc&) {        \
+    set_error("host allocation failed"); \
+    return TDG_ENOMEM;                   \
+  }                                      \
+  catch (const std::exception& ex) {     \
+    set_error(ex.what());                \
+    return TDG_EINVAL;                   \
+  }
+
+#define HIP_OK(call)                                                                \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " in " #call); \
+      return TDG_EHIP;                                                              \
+    }                                                                               \
+  } while (0)
+
+struct tdg_ctx {
+  Topology topo;
+  Quadrature quad;
+  std::vector<Table> tabs;  // index p (0 unused)
+  TentList tents;
+  tdg_opts opts{};
+  int64_t nq = 0, nb = 0;
+  std::vector<int64_t> bpt_off;
+  std::vector<double> bpts;  // nb * (n+1)
+  int max_groups = 1;
+  // staged static tables
+  std::vector<double> hf64;
+  std::vector<int> hi32;
+  struct TabOff {
+    size_t parent, var, fo_ptr, fo_idx, u_ptr, u_idx;  // i32
+    size_t fo_coef, u_coef, fo_coef32;                 // f64 (fo_coef32: floats packed two per double)
+  } toff[kMaxP + 1];
+  size_t o_coords, o_c, o_grad, o_det, o_lam, o_w, o_tb, o_tt, o_bpt;         // f64
+  size_t o_elems, o_v2e_ptr, o_v2e, o_vb_ptr, o_vb, o_vi_ptr, o_vi, o_tentV;  // i32
+  int64_t sizes[TDG_NBUF]{};
+  void* dev[TDG_NBUF]{};
+  bool bound = false;
+  KParams kp{};
+  LdsPlan lp{};
+  size_t w_ex = 0, w_partial = 0, w_out = 0, w_status = 0;  // offsets in doubles inside WORK
+  int nblocks_red = 256;
+};
+
+namespace {
+
+size_t push(std::vector<double>& v, const double* p, size_t n) {
+  size_t off = v.size();
+  v.insert(v.end(), p, p + n);
+  while (v.size() % 32) v.push_back(0.0);  // 256-byte alignment
+  return off;
+}
+size_t push(std::vector<int>& v, const int* p, size_t n) {
+  size_t off = v.size();
+  v.insert(v.end(), p, p + n);
+  while (v.size() % 64) v.push_back(0);
+  return off;
+}
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+// element-record size of the tent kernel (see El<NS> in the kernel)
+int el_size(int n) { return (n + 1) * n + (n + 1) + 2 * n + 5; }
+
+int plan_lds(tdg_ctx* X) {
+  const int n = X->topo.n;
+  const Table& Tm = X->tabs[X->opts.p_max];
+  LdsPlan& L = X->lp;
+  int maxpatch = 0;
+  for (int v = 0; v < X->topo.nv; ++v) maxpatch = std::max(maxpatch, X->topo.v2e_ptr[v + 1] - X->topo.v2e_ptr[v]);
+  L.S = X->max_groups * Tm.NW;
+  L.lda = L.S + 1 + ((L.S + 1) % 2 == 0 ? 1 : 0);
+  L.NWP = Tm.NW | 1;
+  L.M = Tm.M;
+  L.maxpatch = maxpatch;
+  L.ELS = el_size(n);
+  const bool iface = !X->topo.vi.empty();
+  for (int pch : {64, 32, 16}) {
+    L.PCH = pch;
+    L.W1rows = L.PCH * std::max(n + 1, iface ? 4 : 3);
+    int off = 0;
+    auto take = [&](int cnt) {
+      int o = off;
+      off += (cnt + 3) & ~3;
+      return o;
+    };
+    L.off_A = take(L.S * L.lda);
+    L.off_x = take(L.S + kMaxGroups);
+    L.off_mono = take(L.M * L.PCH);
+    int w1 = std::max(L.W1rows * L.NWP, (n + 1) * Tm.M1 + Tm.M);
+    L.off_W1 = take(w1);
+    L.off_W2 = take(L.PCH * (n + 1) + L.PCH * (n + 2) + L.PCH);
+    L.off_el = take(maxpatch * L.ELS);
+    L.off_misc = take(6 * kMaxGroups + 24 + kMaxGroups * L.NWP);
+    L.total = off;
+    if ((size_t)L.total * sizeof(double) + 64 <= 160 * 1024) return TDG_OK;
+  }
+  return fail(TDG_EINVAL, "local system too large for the LDS-resident tent kernel (p_max, speed groups)");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tdg_last_error(void) { return last_error_cstr(); }
+
+int tent_pitch(const tdg_mesh* mesh, const double* c, double T, double gamma, tdg_tents** out) {
+  TDG_TRY_BEGIN
+  if (!mesh || !out) return fail(TDG_EINVAL, "NULL argument");
+  *out = nullptr;
+  Topology topo;
+  std::string err;
+  int rc = build_topology(*mesh, c, topo, err);
+  if (rc) return fail(rc, err);
+  auto* t = new tdg_tents();
+  rc = pitch_tents(topo, T, gamma, t->list, err);
+  if (rc) {
+    delete t;
+    return fail(rc, err);
+  }
+  *out = t;
+  return TDG_OK;
+  TDG_TRY_END
+}
+
+int tent_info(const tdg_tents* t, int32_t* n_layers, int64_t* n_tents, double* max_face_slope) {
+  if (!t) return fail(TDG_EINVAL, "NULL tents");
+  if (n_layers) *n_layers = (int32_t)t->list.layer_ptr.size() - 1;
+  if (n_tents) *n_tents = (int64_t)t->list.V.size();
+  if (max_face_slope) *max_face_slope = t->list.max_slope;
+  return TDG_OK;
+}
+
+int tent_export(const tdg_tents* t, int32_t* vertex, double* t_bot, double* t_top, int64_t* layer_ptr) {
+  if (!t) return fail(TDG_EINVAL, "NULL tents");
+  const auto& L = t->list;
+  if (vertex) std::copy(L.V.begin(), L.V.end(), vertex);
+  if (t_bot) std::copy(L.tb.begin(), L.tb.end(), t_bot);
+  if (t_top) std::copy(L.tt.begin(), L.tt.end(), t_top);
+  if (layer_ptr) std::copy(L.layer_ptr.begin(), L.layer_ptr.end(), layer_ptr);
+  return TDG_OK;
+}
+
+void tent_free(tdg_tents* t) { delete t; }
+
+int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents, const tdg_opts* opts,
+                   tdg_ctx** out) {
+  TDG_TRY_BEGIN
+  if (!mesh || !tents || !opts || !out) return fail(TDG_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (opts->p_max < 1 || opts->p_max > kMaxP) return fail(TDG_EINVAL, "p_max must be in 1..10");
+  if (opts->q < 0 || opts->q > 16) return fail(TDG_EINVAL, "q must be in 0..16");
+  if (opts->layout != 1) return fail(TDG_EINVAL, "layout must be 1 (values at quadrature points)");
+  if (opts->precision != 0 && opts->precision != 1) return fail(TDG_EINVAL, "precision must be 0 or 1");
+  if (!(opts->alpha > 0) || !(opts->beta > 0)) return fail(TDG_EINVAL, "alpha and beta must be positive");
+  auto X = new tdg_ctx();
+  std::unique_ptr<tdg_ctx> guard(X);
+  std::string err;
+  int rc = build_topology(*mesh, c, X->topo, err);
+  if (rc) return fail(rc, err);
+  if (tents->list.n != mesh->dim) return fail(TDG_EINVAL, "tents were pitched on a mesh of another dimension");
+  X->tents = tents->list;
+  for (int v : X->tents.V)
+    if (v < 0 || v >= X->topo.nv) return fail(TDG_EINVAL, "tent vertex out of range");
+  X->opts = *opts;
+  const int n = X->topo.n;
+  const int q = opts->q ? opts->q : opts->p_max;
+  X->quad = simplex_rule(n, q);
+  X->tabs.resize(opts->p_max + 1);
+  for (int p = 1; p <= opts->p_max; ++p) X->tabs[p] = build_table(n, p);
+  X->nq = (int64_t)X->topo.ne * X->quad.Q;
+  // speed groups per patch
+  for (int v = 0; v < X->topo.nv; ++v) {
+    std::vector<double> cs;
+    for (int i = X->topo.v2e_ptr[v]; i < X->topo.v2e_ptr[v + 1]; ++i) {
+      double ce = X->topo.c[X->topo.v2e[i]];
+      if (std::find(cs.begin(), cs.end(), ce) == cs.end()) cs.push_back(ce);
+    }
+    X->max_groups = std::max(X->max_groups, (int)cs.size());
+  }
+  if (X->max_groups > kMaxGroups) return fail(TDG_EINVAL, "more than 8 wave speeds in one vertex patch");
+  // boundary points: replay the front
+  {
+    const int Q = X->quad.Q;
+    const auto& tp = X->tents;
+    const int64_t nt = (int64_t)tp.V.size();
+    X->bpt_off.assign(nt + 1, 0);
+    std::vector<double> tau(X->topo.nv, 0.0);
+    for (int64_t i = 0; i < nt; ++i) {
+      const int V = tp.V[i];
+      if (tau[V] != tp.tb[i]) return fail(TDG_EINVAL, "tent list does not follow the front");
+      const int nf = X->topo.vb_ptr[V + 1] - X->topo.vb_ptr[V];
+      X->bpt_off[i + 1] = X->bpt_off[i] + (int64_t)nf * Q;
+      for (int f = 0; f < nf; ++f) {
+        const int e = X->topo.vb[2 * (X->topo.vb_ptr[V] + f)], k = X->topo.vb[2 * (X->topo.vb_ptr[V] + f) + 1];
+        double P[4][4];
+        for (int d = 0; d < n; ++d) P[0][d] = P[1][d] = X->topo.coords[(size_t)V * n + d];
+        P[0][n] = tp.tb[i];
+        P[1][n] = tp.tt[i];
+        int cc = 2;
+        for (int l = 0; l <= n; ++l) {
+          int w = X->topo.elems[(size_t)e * (n + 1) + l];
+          if (l == k || w == V) continue;
+          for (int d = 0; d < n; ++d) P[cc][d] = X->topo.coords[(size_t)w * n + d];
+          P[cc][n] = tau[w];
+          ++cc;
+        }
+        for (int qq = 0; qq < Q; ++qq) {
+          double y[4] = {0, 0, 0, 0};
+          for (int l = 0; l <= n; ++l)
+            for (int d = 0; d <= n; ++d) y[d] += X->quad.lam[(size_t)qq * (n + 1) + l] * P[l][d];
+          X->bpts.insert(X->bpts.end(), y, y + n + 1);
+        }
+      }
+      tau[V] = tp.tt[i];
+    }
+    X->nb = X->bpt_off[nt];
+  }
+  // stage the static tables
+  const Topology& T = X->topo;
+  X->o_coords = push(X->hf64, T.coords.data(), T.coords.size());
+  X->o_c = push(X->hf64, T.c.data(), T.c.size());
+  X->o_grad = push(X->hf64, T.grad_lam.data(), T.grad_lam.size());
+  X->o_det = push(X->hf64, T.absdet.data(), T.absdet.size());
+  X->o_lam = push(X->hf64, X->quad.lam.data(), X->quad.lam.size());
+  X->o_w = push(X->hf64, X->quad.w.data(), X->quad.w.size());
+  X->o_tb = push(X->hf64, X->tents.tb.data(), X->tents.tb.size());
+  X->o_tt = push(X->hf64, X->tents.tt.data(), X->tents.tt.size());
+  {
+    std::vector<double> tmp(X->bpt_off.size());
+    std::memcpy(tmp.data(), X->bpt_off.data(), tmp.size() * sizeof(double));
+    X->o_bpt = push(X->hf64, tmp.data(), tmp.size());
+  }
+  X->o_elems = push(X->hi32, T.elems.data(), T.elems.size());
+  X->o_v2e_ptr = push(X->hi32, T.v2e_ptr.data(), T.v2e_ptr.size());
+  X->o_v2e = push(X->hi32, T.v2e.data(), T.v2e.size());
+  X->o_vb_ptr = push(X->hi32, T.vb_ptr.data(), T.vb_ptr.size());
+  X->o_vb = push(X->hi32, T.vb.data(), T.vb.size() ? T.vb.size() : 0);
+  X->o_vi_ptr = push(X->hi32, T.vi_ptr.data(), T.vi_ptr.size());
+  X->o_vi = push(X->hi32, T.vi.data(), T.vi.size());
+  X->o_tentV = push(X->hi32, X->tents.V.data(), X->tents.V.size());
+  for (int p = 1; p <= opts->p_max; ++p) {
+    const Table& tb = X->tabs[p];
+    auto& o = X->toff[p];
+    o.parent = push(X->hi32, tb.parent.data(), tb.parent.size());
+    o.var = push(X->hi32, tb.var.data(), tb.var.size());
+    o.fo_ptr = push(X->hi32, tb.fo_ptr.data(), tb.fo_ptr.size());
+    o.fo_idx = push(X->hi32, tb.fo_idx.data(), tb.fo_idx.size());
+    o.u_ptr = push(X->hi32, tb.u_ptr.data(), tb.u_ptr.size());
+    o.u_idx = push(X->hi32, tb.u_idx.data(), tb.u_idx.size());
+    o.fo_coef = push(X->hf64, tb.fo_coef.data(), tb.fo_coef.size());
+    o.u_coef = push(X->hf64, tb.u_coef.data(), tb.u_coef.size());
+    std::vector<float> f32(tb.fo_coef.begin(), tb.fo_coef.end());
+    if (f32.size() % 2) f32.push_back(0.0f);
+    std::vector<double> packed(f32.size() / 2);
+    std::memcpy(packed.data(), f32.data(), f32.size() * sizeof(float));
+    o.fo_coef32 = push(X->hf64, packed.data(), packed.size());
+  }
+  rc = plan_lds(X);
+  if (rc) return rc;
+  // buffer sizes
+  const int64_t nst = X->nq * (n + 2);
+  X->sizes[TDG_BUF_F64] = (int64_t)X->hf64.size() * 8;
+  X->sizes[TDG_BUF_I32] = (int64_t)X->hi32.size() * 4;
+  X->sizes[TDG_BUF_STATE] = nst * 8;
+  X->sizes[TDG_BUF_STATE0] = nst * 8;
+  X->sizes[TDG_BUF_TAU] = (int64_t)T.nv * 8;
+  X->sizes[TDG_BUF_GD] = std::max<int64_t>(X->nb, 1) * 8;
+  X->w_ex = 0;
+  X->w_partial = (size_t)(X->nq * (n + 1) + 31) / 32 * 32;
+  X->w_out = X->w_partial + 2 * X->nblocks_red + 32;
+  X->w_status = X->w_out + 32;
+  X->sizes[TDG_BUF_WORK] = (int64_t)(X->w_status + 32) * 8;
+  X->sizes[TDG_BUF_TENT] = std::max<int64_t>((int64_t)X->tents.V.size(), 1) * 16;
+  guard.release();
+  *out = X;
+  return TDG_OK;
+  TDG_TRY_END
+}
+
+int trefftz_quad_points(const tdg_ctx* X, int64_t* nq, double* xq, double* w) {
+  if (!X || !nq) return fail(TDG_EINVAL, "NULL argument");
+  *nq = X->nq;
+  const int n = X->topo.n, Q = X->quad.Q;
+  for (int e = 0; e < X->topo.ne; ++e) {
+    const int* vs = &X->topo.elems[(size_t)e * (n + 1)];
+    for (int q = 0; q < Q; ++q) {
+      const double* lam = &X->quad.lam[(size_t)q * (n + 1)];
+      if (xq)
+        for (int d = 0; d < n; ++d) {
+          double s = 0.0;
+          for (int k = 0; k <= n; ++k) s += lam[k] * X->topo.coords[(size_t)vs[k] * n + d];
+          xq[((size_t)e * Q + q) * n + d] = s;
+        }
+      if (w) w[(size_t)e * Q + q] = X->quad.w[q] * X->topo.absdet[e];
+    }
+  }
+  return TDG_OK;
+}
+
+int trefftz_boundary_points(const tdg_ctx* X, int64_t* nb, double* xt) {
+  if (!X || !nb) return fail(TDG_EINVAL, "NULL argument");
+  *nb = X->nb;
+  if (xt) std::copy(X->bpts.begin(), X->bpts.end(), xt);
+  return TDG_OK;
+}
+
+int trefftz_buffer_sizes(const tdg_ctx* X, int64_t sizes[TDG_NBUF]) {
+  if (!X || !sizes) return fail(TDG_EINVAL, "NULL argument");
+  for (int i = 0; i < TDG_NBUF; ++i) sizes[i] = X->sizes[i];
+  return TDG_OK;
+}
+
+int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) {
+  if (!X || !dev_ptrs) return fail(TDG_EINVAL, "NULL argument");
+  for (int i = 0; i < TDG_NBUF; ++i) {
+    if (!dev_ptrs[i]) return fail(TDG_EINVAL, "NULL device buffer");
+    if (((uintptr_t)dev_ptrs[i]) % 256) return fail(TDG_EINVAL, "device buffer not 256-byte aligned");
+    X->dev[i] = dev_ptrs[i];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(X->dev[TDG_BUF_F64], X->hf64.data(), X->hf64.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(X->dev[TDG_BUF_I32], X->hi32.data(), X->hi32.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  const double* F = (const double*)X->dev[TDG_BUF_F64];
+  const int* I = (const int*)X->dev[TDG_BUF_I32];
+  KParams& P = X->kp;
+  const Topology& T = X->topo;
+  P.n = T.n;
+  P.nv = T.nv;
+  P.ne = T.ne;
+  P.Q = X->quad.Q;
+  P.pmax = X->opts.p_max;
+  P.ntents = (int)X->tents.V.size();
+  P.precision = X->opts.precision;
+  P.recover_U = X->opts.recover_U;
+  P.alpha = X->opts.alpha;
+  P.beta = X->opts.beta;
+  P.coords = F + X->o_coords;
+  P.c = F + X->o_c;
+  P.grad_lam = F + X->o_grad;
+  P.absdet = F + X->o_det;
+  P.lam_ref = F + X->o_lam;
+  P.w_ref = F + X->o_w;
+  P.tent_tb = F + X->o_tb;
+  P.tent_tt = F + X->o_tt;
+  P.bpt_off = (const long long*)(F + X->o_bpt);
+  P.elems = I + X->o_elems;
+  P.v2e_ptr = I + X->o_v2e_ptr;
+  P.v2e = I + X->o_v2e;
+  P.vb_ptr = I + X->o_vb_ptr;
+  P.vb = I + X->o_vb;
+  P.vi_ptr = I + X->o_vi_ptr;
+  P.vi = I + X->o_vi;
+  P.tent_V = I + X->o_tentV;
+  P.p_per_tent = nullptr;
+  P.state = (double*)X->dev[TDG_BUF_STATE];
+  P.tau = (double*)X->dev[TDG_BUF_TAU];
+  P.gD = (const double*)X->dev[TDG_BUF_GD];
+  double* W = (double*)X->dev[TDG_BUF_WORK];
+  P.status = (int*)(W + X->w_status);
+  P.dissip = (double*)X->dev[TDG_BUF_TENT];
+  P.ir_steps = (int*)((double*)X->dev[TDG_BUF_TENT] + X->tents.V.size());
+  P.work = nullptr;
+  P.work_stride = 0;
+  for (int p = 0; p <= kMaxP; ++p) P.tab[p] = TableDesc{};
+  for (int p = 1; p <= X->opts.p_max; ++p) {
+    const Table& tb = X->tabs[p];
+    const auto& o = X->toff[p];
+    TableDesc& D = P.tab[p];
+    D.p = p;
+    D.NW = tb.NW;
+    D.M = tb.M;
+    D.M1 = tb.M1;
+    D.parent = I + o.parent;
+    D.var = I + o.var;
+    D.fo_ptr = I + o.fo_ptr;
+    D.fo_idx = I + o.fo_idx;
+    D.fo_coef = F + o.fo_coef;
+    D.fo_coef32 = (const float*)(F + o.fo_coef32);
+    D.u_ptr = I + o.u_ptr;
+    D.u_idx = I + o.u_idx;
+    D.u_coef = F + o.u_coef;
+  }
+  if (set_kernel_smem_limit(T.n, (size_t)X->lp.total * 8 + 64)) return fail(TDG_EHIP, "cannot raise the LDS limit");
+  // clear state, front, status, per-tent outputs
+  if (launch_fill(P.state, 0.0, X->nq * (T.n + 2), stream) || launch_fill(P.tau, 0.0, T.nv, stream) ||
+      launch_fill(W + X->w_status, 0.0, 32, stream) ||
+      launch_fill(P.dissip, 0.0, std::max<int64_t>((int64_t)X->tents.V.size(), 1) * 2, stream) ||
+      launch_fill((double*)X->dev[TDG_BUF_GD], 0.0, std::max<int64_t>(X->nb, 1), stream))
+    return fail(TDG_EHIP, "fill kernel launch failed");
+  HIP_OK(hipStreamSynchronize(st));
+  X->bound = true;
+  return TDG_OK;
+}
+
+int trefftz_set_initial(tdg_ctx* X, const double* v0, const double* sigma0, const double* U0, tdg_stream stream) {
+  TDG_TRY_BEGIN
+  if (!X || !v0 || !sigma0) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  const int n = X->topo.n, Q = X->quad.Q, ne = X->topo.ne;
+  std::vector<double> st((size_t)X->nq * (n + 2));
+  for (int e = 0; e < ne; ++e)
+    for (int q = 0; q < Q; ++q) {
+      const size_t i = (size_t)e * Q + q;
+      double* base = &st[(size_t)e * (n + 2) * Q];
+      base[q] = v0[i];
+      for (int d = 0; d < n; ++d) base[(size_t)(1 + d) * Q + q] = sigma0[i * n + d];
+      base[(size_t)(n + 1) * Q + q] = U0 ? U0[i] : 0.0;
+    }
+  for (double x : st)
+    if (!std::isfinite(x)) return fail(TDG_ENAN, "non-finite initial data");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(X->dev[TDG_BUF_STATE0], st.data(), st.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return trefftz_reset(X, stream);
+  TDG_TRY_END
+}
+
+int trefftz_set_boundary(tdg_ctx* X, const double* gD, tdg_stream stream) {
+  if (!X || (!gD && X->nb)) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  for (int64_t i = 0; i < X->nb; ++i)
+    if (!std::isfinite(gD[i])) return fail(TDG_ENAN, "non-finite boundary data");
+  hipStream_t s = (hipStream_t)stream;
+  if (X->nb) HIP_OK(hipMemcpyAsync(X->dev[TDG_BUF_GD], gD, X->nb * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return TDG_OK;
+}
+
+int trefftz_reset(tdg_ctx* X, tdg_stream stream) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(X->dev[TDG_BUF_STATE], X->dev[TDG_BUF_STATE0], X->sizes[TDG_BUF_STATE],
+                        hipMemcpyDeviceToDevice, s));
+  if (launch_fill(X->kp.tau, 0.0, X->topo.nv, stream) ||
+      launch_fill(X->kp.dissip, 0.0, std::max<int64_t>((int64_t)X->tents.V.size(), 1) * 2, stream))
+    return fail(TDG_EHIP, "fill kernel launch failed");
+  return TDG_OK;
+}
+
+int trefftz_layer_solve(tdg_ctx* X, int32_t layer_begin, int32_t layer_end, const int8_t* p_per_tent,
+                        tdg_stream stream) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  const int nl = (int)X->tents.layer_ptr.size() - 1;
+  if (layer_begin < 0 || layer_end > nl || layer_begin > layer_end) return fail(TDG_EINVAL, "layer range out of bounds");
+  if (X->opts.precision != 0) return fail(TDG_EINVAL, "this build solves in FP64 only (precision = 0)");
+  KParams P = X->kp;
+  P.p_per_tent = (const signed char*)p_per_tent;
+  for (int l = layer_begin; l < layer_end; ++l) {
+    const int t0 = (int)X->tents.layer_ptr[l];
+    const int cnt = (int)(X->tents.layer_ptr[l + 1] - X->tents.layer_ptr[l]);
+    if (launch_layer(P, X->lp, t0, cnt, stream)) return fail(TDG_EHIP, "tent kernel launch failed");
+  }
+  return TDG_OK;
+}
+
+static int read_status(tdg_ctx* X, hipStream_t s) {
+  int st = 0;
+  HIP_OK(hipMemcpyAsync(&st, (double*)X->dev[TDG_BUF_WORK] + X->w_status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (st & kStatSingular) return fail(TDG_ESINGULAR, "a local tent system had a zero pivot");
+  if (st & kStatNan) return fail(TDG_ENAN, "non-finite values in a tent solution");
+  if (st & kStatNoConv) return fail(TDG_ENOCONV, "mixed-precision refinement did not converge");
+  if (st & (kStatPatch | kStatGroups | kStatSize))
+    return fail(TDG_EINVAL, "a tent exceeded the kernel's size limits (patch, groups or degree)");
+  return TDG_OK;
+}
+
+int trefftz_status(tdg_ctx* X, tdg_stream stream) {
+  if (!X || !X->bound) return fail(TDG_ESTATE, "context not bound");
+  return read_status(X, (hipStream_t)stream);
+}
+
+int trefftz_eval_error(tdg_ctx* X, const double* v_ex, const double* sigma_ex, double* e_abs, double* e_rel,
+                       tdg_stream stream) {
+  if (!X || !v_ex || !sigma_ex) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  hipStream_t s = (hipStream_t)stream;
+  double* W = (double*)X->dev[TDG_BUF_WORK];
+  const int n = X->topo.n;
+  HIP_OK(hipMemcpyAsync(W + X->w_ex, v_ex, X->nq * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(W + X->w_ex + X->nq, sigma_ex, X->nq * n * 8, hipMemcpyHostToDevice, s));
+  if (launch_norms(X->kp, 0, W + X->w_ex, W + X->w_partial, X->nblocks_red, W + X->w_out, stream))
+    return fail(TDG_EHIP, "reduction launch failed");
+  double out[2];
+  HIP_OK(hipMemcpyAsync(out, W + X->w_out, 16, hipMemcpyDeviceToHost, s));
+  int rc = read_status(X, s);
+  if (rc) return rc;
+  const double ea = std::sqrt(out[0]);
+  if (e_abs) *e_abs = ea;
+  if (e_rel) *e_rel = out[1] > 0 ? ea / std::sqrt(out[1]) : INFINITY;
+  return std::isfinite(ea) ? TDG_OK : fail(TDG_ENAN, "non-finite error");
+}
+
+int trefftz_energy(tdg_ctx* X, double* E_front, double* dissipated, tdg_stream stream) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  hipStream_t s = (hipStream_t)stream;
+  double* W = (double*)X->dev[TDG_BUF_WORK];
+  if (launch_norms(X->kp, 1, nullptr, W + X->w_partial, X->nblocks_red, W + X->w_out, stream))
+    return fail(TDG_EHIP, "reduction launch failed");
+  double out[2];
+  HIP_OK(hipMemcpyAsync(out, W + X->w_out, 16, hipMemcpyDeviceToHost, s));
+  std::vector<double> dis(X->tents.V.size());
+  if (!dis.empty())
+    HIP_OK(hipMemcpyAsync(dis.data(), X->kp.dissip, dis.size() * 8, hipMemcpyDeviceToHost, s));
+  int rc = read_status(X, s);
+  if (rc) return rc;
+  if (E_front) *E_front = out[0];
+  if (dissipated) {
+    double sum = 0.0;
+    for (double d : dis) sum += d;
+    *dissipated = sum;
+  }
+  return TDG_OK;
+}
+
+int trefftz_read_state(tdg_ctx* X, double* v, double* sigma, double* U, tdg_stream stream) {
+  TDG_TRY_BEGIN
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  const int n = X->topo.n, Q = X->quad.Q, ne = X->topo.ne;
+  std::vector<double> st((size_t)X->nq * (n + 2));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(st.data(), X->dev[TDG_BUF_STATE], st.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  for (int e = 0; e < ne; ++e)
+    for (int q = 0; q < Q; ++q) {
+      const size_t i = (size_t)e * Q + q;
+      const double* base = &st[(size_t)e * (n + 2) * Q];
+      if (v) v[i] = base[q];
+      if (sigma)
+        for (int d = 0; d < n; ++d) sigma[i * n + d] = base[(size_t)(1 + d) * Q + q];
+      if (U) U[i] = base[(size_t)(n + 1) * Q + q];
+    }
+  return TDG_OK;
+  TDG_TRY_END
+}
+
+int trefftz_table_info(const tdg_ctx* X, int32_t p, int32_t* N, int32_t* nnz_fields, int32_t* n_mono, int32_t* Q) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (p < 1 || p > X->opts.p_max) return fail(TDG_EINVAL, "p out of range");
+  const Table& t = X->tabs[p];
+  if (N) *N = t.NW + 1;
+  if (nnz_fields) *nnz_fields = (int32_t)t.fo_idx.size();
+  if (n_mono) *n_mono = t.M;
+  if (Q) *Q = X->quad.Q;
+  return TDG_OK;
+}
+
+void trefftz_destroy(tdg_ctx* X) { delete X; }
+
+}  // extern "C"

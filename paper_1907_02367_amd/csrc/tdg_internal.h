@@ -1,0 +1,154 @@
+// Internal data structures shared by the libtdg host code and its HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tdg.h"
+
+namespace tdg {
+
+constexpr int kMaxP = 10;        // highest degree of U^p with tables
+constexpr int kMaxGroups = 8;    // speed groups inside one tent (Sec. 4.2)
+constexpr int kMaxPatch = 64;    // elements in one vertex patch
+constexpr int kBlock = 256;      // threads per workgroup of the tent kernels
+
+// Sparse tables of the Trefftz basis of U^p (c = 1) over the monomials
+// t^k x^alpha, k + |alpha| <= p, ordered by total degree, so the first M1
+// monomials are those of degree <= p - 1.  Monomial i > 0 is
+// mono[parent[i]] * (t if var[i] == 0 else x_var[i]).
+// First-order table (v, sigma) = (dU/dt, -grad U): CSR over rows j*(n+1)+comp
+// for the non-constant functions j = 0..NW-1 (basis functions 1..N-1).
+// U table: CSR over rows j (basis function j+1).
+struct TableDesc {
+  int p, NW, M, M1;
+  const int* parent;
+  const int* var;
+  const int* fo_ptr;
+  const int* fo_idx;
+  const double* fo_coef;
+  const float* fo_coef32;
+  const int* u_ptr;
+  const int* u_idx;
+  const double* u_coef;
+};
+
+// Everything a tent kernel reads or writes.  All pointers are device pointers.
+struct KParams {
+  int n, nv, ne, Q, pmax, ntents;
+  int precision;     // 0 fp64, 1 mixed
+  int recover_U;
+  double alpha, beta;
+  // static geometry
+  const double* coords;    // nv*n
+  const double* c;         // ne
+  const double* grad_lam;  // ne*(n+1)*n
+  const double* absdet;    // ne
+  const double* lam_ref;   // Q*(n+1)
+  const double* w_ref;     // Q
+  const int* elems;        // ne*(n+1)
+  const int* v2e_ptr;      // nv+1
+  const int* v2e;
+  const int* vb_ptr;       // nv+1: boundary facets containing V
+  const int* vb;           // pairs (element, local index of the opposite vertex)
+  const int* vi_ptr;       // nv+1: speed-interface facets containing V
+  const int* vi;           // quadruples (e1, k1, e2, k2), e1 < e2
+  // tents
+  const int* tent_V;
+  const double* tent_tb;
+  const double* tent_tt;
+  const long long* bpt_off;  // ntents+1 offsets into gD
+  const signed char* p_per_tent;  // nullable
+  // dynamic state
+  double* state;  // ne * (n+2) * Q, element-major, then component, then point
+  double* tau;    // nv
+  const double* gD;
+  int* status;    // device error word
+  double* dissip; // ntents, nullable
+  int* ir_steps;  // ntents, nullable (mixed precision)
+  double* work;   // global scratch for systems that do not fit in LDS
+  long long work_stride;  // doubles per workgroup slot
+  TableDesc tab[kMaxP + 1];
+};
+
+// Device status bits (OR-ed by kernels)
+enum : int {
+  kStatSingular = 1,
+  kStatNan = 2,
+  kStatPatch = 4,
+  kStatGroups = 8,
+  kStatNoConv = 16,
+  kStatSize = 32,
+};
+
+// LDS layout of the tent kernel (sizes in doubles), chosen on the host.
+struct LdsPlan {
+  int S;        // largest system size (groups * NW)
+  int lda;      // row stride of the augmented matrix
+  int NWP;      // padded NW
+  int PCH;      // points per chunk
+  int M;        // monomials of degree <= p_max
+  int W1rows;   // rows of the W1 buffer (multiples of PCH)
+  int maxpatch;
+  int ELS;      // doubles per patch element record
+  int off_A, off_x, off_mono, off_W1, off_W2, off_el, off_misc, total;
+};
+
+int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, void* stream);
+int set_kernel_smem_limit(int n, size_t bytes);
+int launch_fill(double* p, double v, long long n, void* stream);
+int launch_norms(const KParams& P, int kind, const double* ex, double* partial, int nblocks, double* out, void* stream);
+
+// ---- host-side components ----------------------------------------------------
+struct Topology {
+  int n = 0, nv = 0, ne = 0;
+  std::vector<double> coords;     // nv*n
+  std::vector<int> elems;         // ne*(n+1)
+  std::vector<double> c;          // ne
+  std::vector<double> grad_lam;   // ne*(n+1)*n
+  std::vector<double> absdet;     // ne
+  std::vector<int> v2e_ptr, v2e;  // patches (ascending element)
+  std::vector<int> nb_ptr, nb;    // neighbours (ascending)
+  std::vector<int> vb_ptr, vb;    // boundary facets at V
+  std::vector<int> vi_ptr, vi;    // interface facets at V
+};
+
+// Builds the topology; returns TDG_OK or an error code with a message.
+int build_topology(const tdg_mesh& m, const double* c, Topology& T, std::string& err);
+
+struct Quadrature {
+  int n = 0, q = 0, Q = 0;
+  std::vector<double> lam;  // Q*(n+1) barycentric coordinates
+  std::vector<double> w;    // Q weights (sum 1/n!)
+};
+void gauss_jacobi01(int q, int a, std::vector<double>& x, std::vector<double>& w);
+Quadrature simplex_rule(int n, int q);
+
+struct Table {
+  int n = 0, p = 0, NW = 0, M = 0, M1 = 0;
+  std::vector<int> parent, var;
+  std::vector<int> expo;  // M*(n+1): k, alpha_1..alpha_n
+  std::vector<int> fo_ptr, fo_idx;
+  std::vector<double> fo_coef;
+  std::vector<int> u_ptr, u_idx;
+  std::vector<double> u_coef;
+};
+Table build_table(int n, int p);
+
+struct TentList {
+  int n = 0;
+  double T = 0, gamma = 0, max_slope = 0;
+  std::vector<int> V;
+  std::vector<double> tb, tt;
+  std::vector<int64_t> layer_ptr;
+};
+int pitch_tents(const Topology& topo, double T, double gamma, TentList& out, std::string& err);
+
+void set_error(const std::string& msg);
+
+}  // namespace tdg
+
+struct tdg_tents {
+  tdg::TentList list;
+};

@@ -1,0 +1,206 @@
+// Exact Trefftz basis tables of U^p (Sec. 3).
+//
+// U(x,t) = sum_{k+|alpha|<=p} a_{k,alpha} x^alpha t^k solves -Lap U + U_tt = 0
+// (c = 1) iff for k >= 2
+//   a_{k,alpha} = 1/(k(k-1)) sum_m (alpha_m+1)(alpha_m+2) a_{k-2,alpha+2e_m}   (eq. 3.1)
+// seeded by monomials: U(.,0) = x^beta, U_t(.,0) = 0 for |beta| <= p, then
+// U(.,0) = 0, U_t(.,0) = x^beta for |beta| <= p-1 (dim = C(p+n,n) + C(p-1+n,n)).
+// Any c is reached by the change of variables of Remark 3.1, applied in the
+// kernels.  Coefficients are computed in exact 64-bit rationals (they stay
+// far below 2^53 for p <= 10) and rounded once to double.
+//
+// Basis order: seed type 0 then type 1, each by |beta| ascending then beta in
+// descending lexicographic order; function 0 is the constant.  The tables
+// hold the first-order fields (v, sigma) = (dU/dt, -grad U) of functions
+// 1..N-1 and the functions themselves (to recover U, Sec. 5).
+#include <algorithm>
+#include <array>
+#include <map>
+#include <numeric>
+
+#include "tdg_internal.h"
+
+namespace tdg {
+
+namespace {
+
+struct Rat {
+  int64_t num = 0, den = 1;
+  Rat() = default;
+  Rat(int64_t a, int64_t b = 1) : num(a), den(b) { norm(); }
+  void norm() {
+    if (den < 0) {
+      num = -num;
+      den = -den;
+    }
+    int64_t g = std::gcd(num < 0 ? -num : num, den);
+    if (g > 1) {
+      num /= g;
+      den /= g;
+    }
+    if (num == 0) den = 1;
+  }
+  Rat operator+(const Rat& o) const {
+    __int128 n = (__int128)num * o.den + (__int128)o.num * den;
+    __int128 d = (__int128)den * o.den;
+    __int128 a = n < 0 ? -n : n, b = d, t;
+    while (b) {
+      t = a % b;
+      a = b;
+      b = t;
+    }
+    if (a > 1) {
+      n /= a;
+      d /= a;
+    }
+    Rat r;
+    r.num = (int64_t)n;
+    r.den = (int64_t)d;
+    r.norm();
+    return r;
+  }
+  Rat mul(int64_t k) const { return Rat((int64_t)((__int128)num * k), den); }
+  Rat div(int64_t k) const { return Rat(num, (int64_t)((__int128)den * k)); }
+  double to_double() const { return (double)num / (double)den; }
+  bool zero() const { return num == 0; }
+};
+
+using Key = std::array<int, 4>;  // k, alpha_1..alpha_3 (unused entries 0)
+
+// multi-indices of length n with |alpha| = deg, descending lexicographic order
+std::vector<Key> multi(int n, int deg) {
+  std::vector<Key> out;
+  Key a{0, 0, 0, 0};
+  // enumerate all with entries in [0, deg]
+  int total = 1;
+  for (int i = 0; i < n; ++i) total *= (deg + 1);
+  for (int idx = 0; idx < total; ++idx) {
+    int r = idx, s = 0;
+    Key al{0, 0, 0, 0};
+    for (int i = n - 1; i >= 0; --i) {
+      al[1 + i] = r % (deg + 1);
+      r /= (deg + 1);
+      s += al[1 + i];
+    }
+    if (s == deg) out.push_back(al);
+  }
+  std::sort(out.begin(), out.end(), [](const Key& x, const Key& y) { return x > y; });
+  (void)a;
+  return out;
+}
+
+}  // namespace
+
+Table build_table(int n, int p) {
+  Table T;
+  T.n = n;
+  T.p = p;
+  // monomials by total degree; inside a degree: k descending, alpha descending lex
+  std::map<Key, int> index;
+  std::vector<Key> mono;
+  for (int d = 0; d <= p; ++d) {
+    for (int k = d; k >= 0; --k)
+      for (Key al : multi(n, d - k)) {
+        al[0] = k;
+        index[al] = (int)mono.size();
+        mono.push_back(al);
+      }
+    if (d == p - 1) T.M1 = (int)mono.size();
+  }
+  if (p == 0) T.M1 = 0;
+  T.M = (int)mono.size();
+  T.parent.assign(T.M, -1);
+  T.var.assign(T.M, 0);
+  T.expo.assign((size_t)T.M * (n + 1), 0);
+  for (int i = 0; i < T.M; ++i) {
+    Key m = mono[i];
+    for (int j = 0; j <= n; ++j) T.expo[(size_t)i * (n + 1) + j] = m[j];
+    if (i == 0) continue;
+    Key par = m;
+    if (m[0] > 0) {
+      par[0]--;
+      T.var[i] = 0;
+    } else {
+      int j = 1;
+      while (m[j] == 0) ++j;
+      par[j]--;
+      T.var[i] = j;
+    }
+    T.parent[i] = index.at(par);
+  }
+  // basis functions
+  std::vector<std::pair<int, Key>> seeds;
+  for (int d = 0; d <= p; ++d)
+    for (Key b : multi(n, d)) seeds.push_back({0, b});
+  for (int d = 0; d + 1 <= p; ++d)
+    for (Key b : multi(n, d)) seeds.push_back({1, b});
+  std::vector<std::map<Key, Rat>> basis;
+  for (auto& sd : seeds) {
+    std::map<Key, Rat> a;
+    Key s = sd.second;
+    s[0] = sd.first;
+    a[s] = Rat(1);
+    for (int k = 2; k <= p; ++k)
+      for (int d = 0; d <= p - k; ++d)
+        for (Key al : multi(n, d)) {
+          Rat acc;
+          for (int m = 0; m < n; ++m) {
+            Key up = al;
+            up[0] = k - 2;
+            up[1 + m] += 2;
+            auto it = a.find(up);
+            if (it != a.end() && !it->second.zero())
+              acc = acc + it->second.mul((int64_t)(al[1 + m] + 1) * (al[1 + m] + 2));
+          }
+          if (!acc.zero()) {
+            Key key = al;
+            key[0] = k;
+            a[key] = acc.div((int64_t)k * (k - 1));
+          }
+        }
+    basis.push_back(a);
+  }
+  const int N = (int)basis.size();
+  T.NW = N - 1;
+  // first-order fields: rows j*(n+1)+comp
+  T.fo_ptr.assign((size_t)T.NW * (n + 1) + 1, 0);
+  T.u_ptr.assign((size_t)T.NW + 1, 0);
+  for (int j = 0; j < T.NW; ++j) {
+    const auto& b = basis[j + 1];
+    for (int comp = 0; comp <= n; ++comp) {
+      std::map<int, Rat> row;
+      for (auto& kv : b) {
+        Key key = kv.first;
+        if (comp == 0) {
+          if (key[0] == 0) continue;
+          Rat v = kv.second.mul(key[0]);
+          key[0]--;
+          row[index.at(key)] = row[index.at(key)] + v;
+        } else {
+          int al = key[comp];
+          if (al == 0) continue;
+          Rat v = kv.second.mul(-al);
+          key[comp]--;
+          row[index.at(key)] = row[index.at(key)] + v;
+        }
+      }
+      for (auto& kv : row)
+        if (!kv.second.zero()) {
+          T.fo_idx.push_back(kv.first);
+          T.fo_coef.push_back(kv.second.to_double());
+        }
+      T.fo_ptr[(size_t)j * (n + 1) + comp + 1] = (int)T.fo_idx.size();
+    }
+    std::map<int, Rat> urow;
+    for (auto& kv : b) urow[index.at(kv.first)] = kv.second;
+    for (auto& kv : urow)
+      if (!kv.second.zero()) {
+        T.u_idx.push_back(kv.first);
+        T.u_coef.push_back(kv.second.to_double());
+      }
+    T.u_ptr[j + 1] = (int)T.u_idx.size();
+  }
+  return T;
+}
+
+}  // namespace tdg

@@ -1,0 +1,114 @@
+"""Host-side checks of libtdg that need no GPU: the library loads and exports
+every symbol of include/tdg.h, its pitcher reproduces the oracle's tent list
+bit for bit (same rule, independent code), its quadrature points agree with
+the oracle's, and invalid inputs are rejected with the documented codes."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.pitcher import pitch
+from oracle.quadrature import simplex_rule
+from workloads import configs as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "tdg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1907_02367_amd import tdg
+
+    L = tdg.lib()
+    names = header_functions()
+    assert len(names) >= 18
+    for nm in names:
+        assert hasattr(L, nm), nm
+        assert nm in tdg.EXPORTS, nm
+
+
+@pytest.mark.parametrize("builder", [
+    lambda: C.cfg1_standing_1d(),
+    lambda: C.cfg2_plane_2d(),
+    lambda: C.cfg4_interface_2d(m=21),
+    lambda: C.cfg5_cube_3d(m=4, regions=2),
+    lambda: C.cfg5_cube_3d(m=3, variant="b"),
+])
+def test_pitcher_bit_equal_to_oracle(builder):
+    from paper_1907_02367_amd import tdg
+
+    pr = builder()
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    tents, lp = pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    assert T.as_list() == tents
+    assert T.layer_ptr.tolist() == lp
+    assert 0 < T.max_slope < 1
+
+
+def test_cfg1_tent_counts():
+    from paper_1907_02367_amd import tdg
+
+    pr = C.cfg1_standing_1d()
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    assert (T.n_tents, T.n_layers) == (281, 33)
+
+
+@pytest.mark.parametrize("n,p,q", [(1, 3, 3), (2, 4, 4), (2, 3, 9), (3, 3, 3)])
+def test_quadrature_points_match_oracle(n, p, q):
+    from paper_1907_02367_amd import tdg
+
+    pr = {1: C.cfg1_standing_1d(n_elems=5), 2: C.cfg2_plane_2d(m=6), 3: C.cfg5_cube_3d(m=2, variant="b")}[n]
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p, q=q, bind=False)
+    xq, w = ctx.quad_points()
+    lam, wr = simplex_rule(n, q)
+    X = np.einsum("qk,ekd->eqd", lam, pr.coords[pr.elems]).reshape(-1, n)
+    assert np.abs(xq - X).max() < 1e-14
+    vol = np.abs(np.linalg.det(pr.coords[pr.elems][:, 1:] - pr.coords[pr.elems][:, :1]))
+    assert np.abs(w - (wr[None, :] * vol[:, None]).ravel()).max() < 1e-15 * max(1.0, vol.max())
+
+
+def test_boundary_points_on_boundary_and_in_time():
+    from paper_1907_02367_amd import tdg
+
+    pr = C.cfg2_plane_2d(m=8)
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, bind=False)
+    bx = ctx.boundary_points()
+    assert ctx.nb > 0 and bx.shape == (ctx.nb, 3)
+    on = (np.abs(bx[:, 0]) < 1e-12) | (np.abs(bx[:, 0] - 1) < 1e-12) | (np.abs(bx[:, 1]) < 1e-12) | (np.abs(bx[:, 1] - 1) < 1e-12)
+    assert on.all()
+    assert (bx[:, 2] > 0).all() and (bx[:, 2] < pr.T).all()
+
+
+def test_errors_are_reported_not_raised_across_the_abi():
+    from paper_1907_02367_amd import tdg
+
+    pr = C.cfg2_plane_2d(m=8)
+    with pytest.raises(tdg.TdgError) as ei:
+        tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, 1.5)
+    assert ei.value.name == "TDG_ENONCAUSAL"
+    bad_c = pr.c.copy()
+    bad_c[3] = 0.0
+    with pytest.raises(tdg.TdgError) as ei:
+        tdg.tent_pitch(pr.coords, pr.elems, bad_c, pr.T, pr.gamma)
+    assert ei.value.name == "TDG_EINVAL"
+    coords = pr.coords.copy()
+    e0 = pr.elems[0]
+    coords[e0[2]] = 0.5 * (coords[e0[0]] + coords[e0[1]])  # flatten one triangle
+    with pytest.raises(tdg.TdgError) as ei:
+        tdg.tent_pitch(coords, pr.elems, pr.c, pr.T, pr.gamma)
+    assert ei.value.name == "TDG_EINVAL"
+    with pytest.raises(tdg.TdgError) as ei:
+        tdg.tent_pitch(pr.coords, pr.elems, pr.c, -1.0, pr.gamma)
+    assert ei.value.name == "TDG_EINVAL"
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    for p in (0, 11):
+        with pytest.raises(tdg.TdgError) as ei:
+            tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p, bind=False)
+        assert ei.value.name == "TDG_EINVAL"
