@@ -58,7 +58,7 @@ struct tdg_ctx {
   std::vector<double> hf64;
   std::vector<int> hi32;
   struct TabOff {
-    size_t parent, var, fo_ptr, fo_idx, u_ptr, u_idx;  // i32
+    size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx;  // i32
     size_t fo_coef, u_coef, fo_coef32;                 // f64 (fo_coef32: floats packed two per double)
   } toff[kMaxP + 1];
   size_t o_coords, o_c, o_grad, o_det, o_lam, o_w, o_tb, o_tt, o_bpt;         // f64
@@ -68,7 +68,8 @@ struct tdg_ctx {
   bool bound = false;
   KParams kp{};
   LdsPlan lp{};
-  size_t w_ex = 0, w_partial = 0, w_out = 0, w_status = 0;  // offsets in doubles inside WORK
+  size_t w_ex = 0, w_partial = 0, w_out = 0, w_status = 0, w_sys = 0;  // offsets in doubles inside WORK
+  int64_t sys_stride = 0;  // doubles per workgroup for systems kept in global memory
   int nblocks_red = 256;
 };
 
@@ -103,32 +104,51 @@ int plan_lds(tdg_ctx* X) {
   for (int v = 0; v < X->topo.nv; ++v) maxpatch = std::max(maxpatch, X->topo.v2e_ptr[v + 1] - X->topo.v2e_ptr[v]);
   L.S = X->max_groups * Tm.NW;
   L.lda = L.S + 1 + ((L.S + 1) % 2 == 0 ? 1 : 0);
-  L.NWP = Tm.NW | 1;
+  const int ntd = (Tm.NW + 15) / 16;
+  L.NWP = ntd * 16 + 1;
+  const int ntiles = ntd * (ntd + 1) / 2;
+  int tpw = (ntiles + kBlock / 64 - 1) / (kBlock / 64);
+  L.TPW = 1;
+  while (L.TPW < tpw) L.TPW *= 2;
+  if (L.TPW > 16) return fail(TDG_EINVAL, "degree too high for the tent kernel (more than 16 Gram tiles per wave)");
   L.M = Tm.M;
   L.maxpatch = maxpatch;
   L.ELS = el_size(n);
-  const bool iface = !X->topo.vi.empty();
-  for (int pch : {64, 32, 16}) {
-    L.PCH = pch;
-    L.W1rows = L.PCH * std::max(n + 1, iface ? 4 : 3);
-    int off = 0;
-    auto take = [&](int cnt) {
-      int o = off;
-      off += (cnt + 3) & ~3;
-      return o;
-    };
-    L.off_A = take(L.S * L.lda);
-    L.off_x = take(L.S + kMaxGroups);
-    L.off_mono = take(L.M * L.PCH);
-    int w1 = std::max(L.W1rows * L.NWP, (n + 1) * Tm.M1 + Tm.M);
-    L.off_W1 = take(w1);
-    L.off_W2 = take(L.PCH * (n + 1) + L.PCH * (n + 2) + L.PCH);
-    L.off_el = take(maxpatch * L.ELS);
-    L.off_misc = take(6 * kMaxGroups + 24 + kMaxGroups * L.NWP);
-    L.total = off;
-    if ((size_t)L.total * sizeof(double) + 64 <= 160 * 1024) return TDG_OK;
+  const int nfp = Tm.NW * (n + 1) + 1, nnz = (int)Tm.fo_idx.size(), nup = Tm.NW + 1, unz = (int)Tm.u_idx.size();
+  const int nex = Tm.M * (n + 1);
+  L.tab_int_dbl = (nfp + nnz + nup + unz + nex + 1) / 2;
+  const int tab_dbl = L.tab_int_dbl + nnz + unz;
+  struct Choice {
+    bool a, t;
+    int min_pch;
+  };
+  const Choice order[4] = {{true, true, 16}, {true, false, 16}, {false, true, 4}, {false, false, 4}};
+  for (const Choice& ch : order) {
+    for (int pch : {64, 32, 16, 8, 4}) {
+      if (pch < ch.min_pch) continue;
+      L.PCH = pch;
+      L.A_in_lds = ch.a;
+      L.tab_in_lds = ch.t;
+      int off = 0;
+      auto take = [&](long long cnt) {
+        int o = off;
+        off += (int)((cnt + 3) & ~3LL);
+        return o;
+      };
+      L.off_x = take(L.S + kMaxGroups);
+      L.off_el = take((long long)maxpatch * L.ELS);
+      L.off_misc = take(5 * kMaxGroups + 24 + (long long)kMaxGroups * L.NWP);
+      L.off_pt = take((long long)pch * (2 * (n + 1) + 1 + (n + 2) + n + 1));
+      L.off_pow = take(2LL * pch * (n + 1) * (X->opts.p_max + 1));
+      L.off_mono = take((long long)Tm.M * 2 * pch);
+      L.off_W1 = take(std::max<long long>((long long)pch * (n + 3) * L.NWP, (n + 1) * Tm.M1 + Tm.M));
+      L.off_tab = ch.t ? take(tab_dbl) : 0;
+      L.off_A = ch.a ? take((long long)L.S * L.lda) : 0;
+      L.total = off;
+      if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) return TDG_OK;
+    }
   }
-  return fail(TDG_EINVAL, "local system too large for the LDS-resident tent kernel (p_max, speed groups)");
+  return fail(TDG_EINVAL, "tent kernel working set does not fit in LDS");
 }
 
 }  // namespace
@@ -277,6 +297,7 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     auto& o = X->toff[p];
     o.parent = push(X->hi32, tb.parent.data(), tb.parent.size());
     o.var = push(X->hi32, tb.var.data(), tb.var.size());
+    o.expo = push(X->hi32, tb.expo.data(), tb.expo.size());
     o.fo_ptr = push(X->hi32, tb.fo_ptr.data(), tb.fo_ptr.size());
     o.fo_idx = push(X->hi32, tb.fo_idx.data(), tb.fo_idx.size());
     o.u_ptr = push(X->hi32, tb.u_ptr.data(), tb.u_ptr.size());
@@ -303,7 +324,14 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   X->w_partial = (size_t)(X->nq * (n + 1) + 31) / 32 * 32;
   X->w_out = X->w_partial + 2 * X->nblocks_red + 32;
   X->w_status = X->w_out + 32;
-  X->sizes[TDG_BUF_WORK] = (int64_t)(X->w_status + 32) * 8;
+  X->w_sys = X->w_status + 32;
+  {
+    int64_t widest = 0;
+    for (size_t l = 0; l + 1 < X->tents.layer_ptr.size(); ++l)
+      widest = std::max<int64_t>(widest, X->tents.layer_ptr[l + 1] - X->tents.layer_ptr[l]);
+    X->sys_stride = X->lp.A_in_lds ? 0 : ((int64_t)X->lp.S * X->lp.lda + 31) / 32 * 32;
+    X->sizes[TDG_BUF_WORK] = (int64_t)(X->w_sys + X->sys_stride * widest) * 8;
+  }
   X->sizes[TDG_BUF_TENT] = std::max<int64_t>((int64_t)X->tents.V.size(), 1) * 16;
   guard.release();
   *out = X;
@@ -394,8 +422,8 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
   P.status = (int*)(W + X->w_status);
   P.dissip = (double*)X->dev[TDG_BUF_TENT];
   P.ir_steps = (int*)((double*)X->dev[TDG_BUF_TENT] + X->tents.V.size());
-  P.work = nullptr;
-  P.work_stride = 0;
+  P.work = W + X->w_sys;
+  P.work_stride = X->sys_stride;
   for (int p = 0; p <= kMaxP; ++p) P.tab[p] = TableDesc{};
   for (int p = 1; p <= X->opts.p_max; ++p) {
     const Table& tb = X->tabs[p];
@@ -405,8 +433,11 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
     D.NW = tb.NW;
     D.M = tb.M;
     D.M1 = tb.M1;
+    D.fo_nnz = (int)tb.fo_idx.size();
+    D.u_nnz = (int)tb.u_idx.size();
     D.parent = I + o.parent;
     D.var = I + o.var;
+    D.expo = I + o.expo;
     D.fo_ptr = I + o.fo_ptr;
     D.fo_idx = I + o.fo_idx;
     D.fo_coef = F + o.fo_coef;

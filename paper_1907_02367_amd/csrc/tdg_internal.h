@@ -22,9 +22,10 @@ constexpr int kBlock = 256;      // threads per workgroup of the tent kernels
 // for the non-constant functions j = 0..NW-1 (basis functions 1..N-1).
 // U table: CSR over rows j (basis function j+1).
 struct TableDesc {
-  int p, NW, M, M1;
+  int p, NW, M, M1, fo_nnz, u_nnz;
   const int* parent;
   const int* var;
+  const int* expo;  // M*(n+1) exponents (k, alpha) of each monomial
   const int* fo_ptr;
   const int* fo_idx;
   const double* fo_coef;
@@ -84,15 +85,18 @@ enum : int {
 
 // LDS layout of the tent kernel (sizes in doubles), chosen on the host.
 struct LdsPlan {
-  int S;        // largest system size (groups * NW)
-  int lda;      // row stride of the augmented matrix
-  int NWP;      // padded NW
-  int PCH;      // points per chunk
-  int M;        // monomials of degree <= p_max
-  int W1rows;   // rows of the W1 buffer (multiples of PCH)
+  int S;         // largest system size (groups * NW)
+  int lda;       // row stride of the augmented matrix
+  int NWP;       // row stride of the Gram operand (16-padded NW, odd)
+  int PCH;       // points per chunk
+  int M;         // monomials of degree <= p_max
+  int TPW;       // Gram tiles per wave
   int maxpatch;
-  int ELS;      // doubles per patch element record
-  int off_A, off_x, off_mono, off_W1, off_W2, off_el, off_misc, total;
+  int ELS;       // doubles per patch element record
+  int A_in_lds;  // 1: system in LDS; 0: in the global scratch slot of the workgroup
+  int tab_in_lds;
+  int tab_int_dbl;  // doubles occupied by the integer part of a staged table
+  int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, total;
 };
 
 int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, void* stream);

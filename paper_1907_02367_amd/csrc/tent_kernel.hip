@@ -1,25 +1,26 @@
-// Per-tent Trefftz-DG solve on gfx950: one workgroup per tent, all tents of a
-// layer in one launch (tents of a layer share no element, Sec. 2.2).
+// Per-tent Trefftz-DG solve on gfx950: one workgroup (4 waves) per tent, all
+// tents of a layer in one launch (tents of a layer share no element, Sec. 2.2).
 //
 // For the tent at vertex V with bottom front phi_old and top front phi_new
 // (phi_new = phi_old + (t_top - t_bot) lambda_V on each patch element):
-//   1. gather the patch: vertex coordinates, front heights, grad phi, speeds;
-//      group the elements by speed (Sec. 4.2)
-//   2. per speed group, shift and scale the c = 1 Trefftz basis (Remark 3.1):
-//      xh = (x - X_V)/h, th = c (t - t_mid)/h with h the anisotropic diameter
-//      (eq. 3.3) of the tent; v = c dU/dth, sigma = -grad_xh U, U_j = h Uhat_j
-//   3. top facets (eq. 4.1 written on the graph t = phi(x)):
-//        A += sum_q w [c^-2 v_i v_j + s_i.s_j - (v_i s_j + v_j s_i).grad phi_new]
-//      computed as Psi^T Psi with Psi = sqrt(w) D^(1/2) B Phi, where
-//      G = [[c^-2, -g^T], [-g, I]] = B^T D B, B = [[1, 0], [-g, I]],
-//      D = diag(c^-2 - |g|^2, I) (positive on space-like facets)
-//   4. bottom facets: rhs_i += sum_q w Phi_i(bottom)^T G_old u_bot
-//      and the recovery row of U (Sec. 5): mean of U over the bottom
-//   5. Dirichlet faces: A_ij += w v_i (alpha v_j + s_j.n), rhs_i += w g_D (alpha v_i - s_i.n)
-//   6. speed interfaces: centred fluxes with penalties (Sec. 4.2)
-//   7. LU with partial pivoting, back substitution, U constants
-//   8. evaluate (v, sigma, U) at the top points and overwrite the stored values;
-//      tau_V = t_top
+//   1. gather the patch (coordinates, front heights, grad phi, speeds); group
+//      the elements by speed (Sec. 4.2); anisotropic diameter per group (eq. 3.3)
+//   2. per group, the c = 1 Trefftz basis is shifted and scaled (Remark 3.1):
+//      xh = (x - X_V)/h, th = c (t - t_mid)/h; v = c dU/dth, sigma = -grad_xh U,
+//      U_j = h Uhat_j.  The points of all elements of the group form one list,
+//      processed in chunks of PCH points:
+//        - top facets (eq. 4.1 on the graph t = phi_new(x)):
+//              A += sum_q w Phi^T G_new Phi = Psi^T Psi,  Psi = sqrt(w) D^(1/2) B Phi,
+//          G = [[c^-2, -g^T], [-g, I]] = B^T D B, B = [[1, 0], [-g, I]],
+//          D = diag(c^-2 - |g|^2, I) (positive on space-like facets).
+//          The Gram Psi^T Psi runs on the FP64 matrix cores (16x16x4 tiles).
+//        - bottom facets: rhs_i += sum_q w Phi_i(bottom)^T G_old u_bot, and the
+//          U recovery row (Sec. 5): the mean of U over the bottom facets.
+//   3. Dirichlet faces: A_ij += w v_i (alpha v_j + s_j.n), rhs_i += w g_D (alpha v_i - s_i.n);
+//      speed interfaces: centred fluxes with penalties (Sec. 4.2).
+//   4. LU with partial pivoting (one wave for systems up to 64 unknowns, the
+//      whole workgroup otherwise), back substitution, U constants.
+//   5. (v, sigma, U) at the top points overwrite the stored values; tau_V = t_top.
 #include <hip/hip_runtime.h>
 
 #include "tdg_internal.h"
@@ -28,13 +29,15 @@ namespace tdg {
 
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 template <int NS>
 struct El {
-  // offsets inside one patch-element record
-  static constexpr int X = 0;                       // (NS+1) vertices x NS coords
-  static constexpr int TAU = (NS + 1) * NS;         // NS+1 heights
-  static constexpr int GOLD = TAU + NS + 1;         // NS
-  static constexpr int GNEW = GOLD + NS;            // NS
+  // offsets inside one patch-element record (doubles)
+  static constexpr int X = 0;                // (NS+1) vertices x NS coordinates
+  static constexpr int TAU = (NS + 1) * NS;  // NS+1 front heights
+  static constexpr int GOLD = TAU + NS + 1;  // grad phi_old
+  static constexpr int GNEW = GOLD + NS;     // grad phi_new
   static constexpr int C = GNEW + NS;
   static constexpr int DET = C + 1;
   static constexpr int GRP = DET + 1;
@@ -44,68 +47,179 @@ struct El {
 };
 
 __device__ inline void atomic_max_nonneg(double* addr, double v) {
-  // non-negative doubles order like their bit patterns
   atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-// Monomials t^k x^alpha of one point (thread-private column of mono).
-__device__ inline void eval_mono(const TableDesc& T, int count, double* mono, int PCH, int pt, const double* var) {
-  mono[pt] = 1.0;
-  for (int i = 1; i < count; ++i) mono[i * PCH + pt] = mono[T.parent[i] * PCH + pt] * var[T.var[i]];
+// ordering of LDS accesses inside one wave (no workgroup barrier needed)
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Fields (vhat, sigmahat) of non-constant basis function j at one point.
+// Table of one degree, possibly staged in LDS.
+struct Tab {
+  const int* fo_ptr;
+  const int* fo_idx;
+  const double* fo_coef;
+  const int* u_ptr;
+  const int* u_idx;
+  const double* u_coef;
+  const int* expo;  // M*(NS+1) exponents (k, alpha)
+  int NW, M, M1;
+};
+
+// Monomials of points [0, npt) from their coordinates var[pt*(NS+1) + v]
+// (v = 0: th, v >= 1: xh_v): first the powers, then each monomial as a product
+// of powers (flat parallel over (point, monomial)).  mono has row stride ld.
 template <int NS>
-__device__ inline void eval_fields(const TableDesc& T, int j, const double* mono, int PCH, int pt, double* out) {
+__device__ inline void monomials(const Tab& T, int count, int p, const double* var, double* pw, double* mono,
+                                 int ld, int npt) {
+  const int P1 = p + 1;
+  for (int i = threadIdx.x; i < npt * (NS + 1); i += blockDim.x) {
+    const int pt = i / (NS + 1), v = i % (NS + 1);
+    const double x = var[pt * (NS + 1) + v];
+    double* o = pw + (pt * (NS + 1) + v) * P1;
+    double a = 1.0;
+    for (int e = 0; e < P1; ++e) {
+      o[e] = a;
+      a *= x;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < npt * count; i += blockDim.x) {
+    const int m = i / npt, pt = i % npt;
+    const int* ex = T.expo + m * (NS + 1);
+    const double* w = pw + pt * (NS + 1) * P1;
+    double val = w[ex[0]];
+#pragma unroll
+    for (int v = 1; v <= NS; ++v) val *= w[v * P1 + ex[v]];
+    mono[m * ld + pt] = val;
+  }
+}
+
+template <int NS>
+__device__ inline void fields(const Tab& T, int j, const double* mono, int ld, int pt, double* out) {
 #pragma unroll
   for (int comp = 0; comp <= NS; ++comp) {
-    double acc = 0.0;
     const int r = j * (NS + 1) + comp;
-    for (int e = T.fo_ptr[r]; e < T.fo_ptr[r + 1]; ++e) acc += T.fo_coef[e] * mono[T.fo_idx[e] * PCH + pt];
+    double acc = 0.0;
+    for (int e = T.fo_ptr[r]; e < T.fo_ptr[r + 1]; ++e) acc += T.fo_coef[e] * mono[T.fo_idx[e] * ld + pt];
     out[comp] = acc;
   }
 }
 
-__device__ inline double eval_u(const TableDesc& T, int j, const double* mono, int PCH, int pt) {
+__device__ inline double ufield(const Tab& T, int j, const double* mono, int ld, int pt) {
   double acc = 0.0;
-  for (int e = T.u_ptr[j]; e < T.u_ptr[j + 1]; ++e) acc += T.u_coef[e] * mono[T.u_idx[e] * PCH + pt];
+  for (int e = T.u_ptr[j]; e < T.u_ptr[j + 1]; ++e) acc += T.u_coef[e] * mono[T.u_idx[e] * ld + pt];
   return acc;
 }
 
-// C[i][j] += sum_k L[k][i] R[k][j] for i, j < NW over nrow rows (LDS, row stride NWP)
-__device__ inline void acc_block(double* A, int lda, int r0, int c0, const double* L, const double* R, int nrow,
-                                 int NWP, int NW) {
-  for (int idx = threadIdx.x; idx < NW * NW; idx += blockDim.x) {
-    const int i = idx / NW, j = idx % NW;
-    double acc = 0.0;
-    for (int k = 0; k < nrow; ++k) acc += L[k * NWP + i] * R[k * NWP + j];
-    A[(r0 + i) * lda + c0 + j] += acc;
+// LU with partial pivoting of the augmented S x (S+1) matrix by one wave
+// (S <= 64): lane i owns row i.  Returns false on a zero pivot.
+__device__ inline bool wave_lu_solve(double* A, int lda, int S, double* x) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 0; k < S; ++k) {
+    double v = (lane >= k && lane < S) ? fabs(A[lane * lda + k]) : -1.0;
+    int bi = lane;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > v || (ov == v && oi < bi)) {
+        v = ov;
+        bi = oi;
+      }
+    }
+    if (bi != k) {
+      for (int j = k + lane; j <= S; j += 64) {
+        const double t = A[k * lda + j];
+        A[k * lda + j] = A[bi * lda + j];
+        A[bi * lda + j] = t;
+      }
+    }
+    wave_sync();
+    const double piv = A[k * lda + k];
+    if (piv == 0.0) return false;
+    if (lane > k && lane < S) {
+      const double l = A[lane * lda + k] / piv;
+      A[lane * lda + k] = l;
+      for (int j = k + 1; j <= S; ++j) A[lane * lda + j] -= l * A[k * lda + j];
+    }
+    wave_sync();
   }
+  for (int k = S - 1; k >= 0; --k) {
+    const double xk = A[k * lda + S] / A[k * lda + k];
+    if (lane == 0) x[k] = xk;
+    if (lane < k) A[lane * lda + S] -= A[lane * lda + k] * xk;
+    wave_sync();
+  }
+  return true;
+}
+
+// Workgroup LU with partial pivoting of the augmented S x (S+1) matrix
+// (LDS or global memory).  s_piv: shared scratch.  Returns false on a zero pivot.
+__device__ inline bool block_lu_solve(double* A, long long lda, int S, double* x, int* s_piv) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < S; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = S;
+      for (int r = k + tid; r < S; r += 64) {
+        const double v = fabs(A[r * lda + k]);
+        if (v > best) {
+          best = v;
+          bi = r;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) *s_piv = bi;
+    }
+    __syncthreads();
+    const int pr = *s_piv;
+    if (pr != k)
+      for (int j = k + tid; j <= S; j += blockDim.x) {
+        const double t = A[k * lda + j];
+        A[k * lda + j] = A[pr * lda + j];
+        A[pr * lda + j] = t;
+      }
+    __syncthreads();
+    const double piv = A[k * lda + k];
+    if (piv == 0.0) return false;
+    // four threads per row: multiplier, then the row update (the multiplier
+    // column k is written only after the barrier below)
+    for (int i = k + 1 + tid / 4; i < S; i += blockDim.x / 4) {
+      const double l = A[i * lda + k] / piv;
+      for (int j = k + 1 + (tid & 3); j <= S; j += 4) A[i * lda + j] -= l * A[k * lda + j];
+    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < S; i += blockDim.x) A[i * lda + k] /= piv;
+    __syncthreads();
+  }
+  for (int k = S - 1; k >= 0; --k) {
+    const double xk = A[k * lda + S] / A[k * lda + k];
+    if (tid == 0) x[k] = xk;
+    for (int i = tid; i < k; i += blockDim.x) A[i * lda + S] -= A[i * lda + k] * xk;
+    __syncthreads();
+  }
+  return true;
 }
 
 }  // namespace
 
-template <int NS>
+template <int NS, int TPW>
 __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L, int t0) {
   extern __shared__ double lds[];
-  double* A = lds + L.off_A;
-  double* xs = lds + L.off_x;
-  double* mono = lds + L.off_mono;
-  double* W1 = lds + L.off_W1;
-  double* W2 = lds + L.off_W2;
-  double* EL = lds + L.off_el;
-  double* MS = lds + L.off_misc;
-  // misc layout
-  double* gc = MS;                    // kMaxGroups speeds
-  double* gh = gc + kMaxGroups;       // kMaxGroups diameters
-  double* A00 = gh + kMaxGroups;      // kMaxGroups
-  double* r0 = A00 + kMaxGroups;      // kMaxGroups
-  double* a0 = r0 + kMaxGroups;       // kMaxGroups
-  double* fsc = a0 + kMaxGroups;      // face scalars: measure, normal, simplex vertices (24)
-  double* A0 = fsc + 24;              // kMaxGroups x NWP
-  __shared__ int s_m, s_piv, s_err;
-
+  __shared__ int s_m, s_piv, s_err, s_goff[kMaxGroups + 1];
+  __shared__ int s_gel[kMaxPatch];
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int tent = t0 + blockIdx.x;
   const int V = P.tent_V[tent];
   const double tb = P.tent_tb[tent], tt = P.tent_tt[tent];
@@ -117,17 +231,87 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
   const int Q = P.Q;
   const int PCH = L.PCH;
   const int NWP = L.NWP;
-  const int lda = L.lda;
   const int ELS = L.ELS;
   if (p < 1 || p > P.pmax || npatch > L.maxpatch) {
-    if (tid == 0) atomicOr(P.status, p < 1 || p > P.pmax ? kStatSize : kStatPatch);
+    if (tid == 0) atomicOr(P.status, (p < 1 || p > P.pmax) ? kStatSize : kStatPatch);
     return;
   }
-  const TableDesc T = P.tab[p];
+  // ---- LDS carve-up --------------------------------------------------------------
+  double* xs = lds + L.off_x;
+  double* EL = lds + L.off_el;
+  double* MS = lds + L.off_misc;
+  double* gc = MS;
+  double* gh = gc + kMaxGroups;
+  double* A00 = gh + kMaxGroups;
+  double* r0 = A00 + kMaxGroups;
+  double* a0 = r0 + kMaxGroups;
+  double* fsc = a0 + kMaxGroups;  // 24: face measure, normal, simplex vertices
+  double* A0 = fsc + 24;          // kMaxGroups x NWP
+  double* PV = lds + L.off_pt;    // 2*PCH x (NS+1): top then bottom coordinates
+  double* PW = PV + 2 * PCH * (NS + 1);  // PCH weights
+  double* PD = PW + PCH;                 // PCH x (NS+2): weighted bottom data, w*U_b
+  double* PG = PD + PCH * (NS + 2);      // PCH x NS: grad phi_new at the point
+  double* PS = PG + PCH * NS;            // PCH: c^-2 - |g_new|^2
+  double* POW = lds + L.off_pow;         // 2*PCH x (NS+1) x (pmax+1)
+  double* MT = lds + L.off_mono;         // M x 2*PCH monomials (top points, then bottom points)
+  double* W1 = lds + L.off_W1;           // PSI: PCH*(NS+1) rows, RB: PCH rows, UB: PCH rows (row stride NWP)
+  double* PSI = W1;
+  double* RB = W1 + PCH * (NS + 1) * NWP;
+  double* UB = RB + PCH * NWP;
+  // system: LDS or this workgroup's slot of the global scratch
+  const long long lda = L.lda;
+  double* A = L.A_in_lds ? lds + L.off_A : P.work + (long long)blockIdx.x * P.work_stride;
+
+  // ---- table of degree p (staged in LDS when it fits) ----------------------------
+  Tab T;
+  {
+    const TableDesc& D = P.tab[p];
+    T.NW = D.NW;
+    T.M = D.M;
+    T.M1 = D.M1;
+    if (L.tab_in_lds) {
+      int* ti = reinterpret_cast<int*>(lds + L.off_tab);
+      double* td = lds + L.off_tab + L.tab_int_dbl;
+      const int nfp = D.NW * (NS + 1) + 1, nnz = D.fo_nnz, nup = D.NW + 1, unz = D.u_nnz, nex = D.M * (NS + 1);
+      int* t_fp = ti;
+      int* t_fi = t_fp + nfp;
+      int* t_up = t_fi + nnz;
+      int* t_ui = t_up + nup;
+      int* t_ex = t_ui + unz;
+      double* t_fc = td;
+      double* t_uc = td + nnz;
+      for (int i = tid; i < nfp; i += blockDim.x) t_fp[i] = D.fo_ptr[i];
+      for (int i = tid; i < nnz; i += blockDim.x) {
+        t_fi[i] = D.fo_idx[i];
+        t_fc[i] = D.fo_coef[i];
+      }
+      for (int i = tid; i < nup; i += blockDim.x) t_up[i] = D.u_ptr[i];
+      for (int i = tid; i < unz; i += blockDim.x) {
+        t_ui[i] = D.u_idx[i];
+        t_uc[i] = D.u_coef[i];
+      }
+      for (int i = tid; i < nex; i += blockDim.x) t_ex[i] = D.expo[i];
+      T.fo_ptr = t_fp;
+      T.fo_idx = t_fi;
+      T.fo_coef = t_fc;
+      T.u_ptr = t_up;
+      T.u_idx = t_ui;
+      T.u_coef = t_uc;
+      T.expo = t_ex;
+    } else {
+      T.fo_ptr = D.fo_ptr;
+      T.fo_idx = D.fo_idx;
+      T.fo_coef = D.fo_coef;
+      T.u_ptr = D.u_ptr;
+      T.u_idx = D.u_idx;
+      T.u_coef = D.u_coef;
+      T.expo = D.expo;
+    }
+  }
   const int NW = T.NW;
   const double* XV = P.coords + (size_t)V * NS;
 
-  // ---- 1. patch records -------------------------------------------------------
+  // ---- 1. patch records, speed groups, diameters ---------------------------------
   for (int i = tid; i < npatch; i += blockDim.x) {
     const int e = P.v2e[pb + i];
     double* R = EL + i * ELS;
@@ -184,6 +368,14 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
       }
       EL[i * ELS + El<NS>::GRP] = (double)g;
     }
+    // element lists per group, in patch order
+    int c = 0;
+    for (int r = 0; r < m; ++r) {
+      s_goff[r] = c;
+      for (int i = 0; i < npatch; ++i)
+        if ((int)EL[i * ELS + El<NS>::GRP] == r) s_gel[c++] = i;
+    }
+    s_goff[m] = c;
     s_m = m;
   }
   __syncthreads();
@@ -193,15 +385,12 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     if (tid == 0) atomicOr(P.status, s_err ? s_err : kStatSize);
     return;
   }
-
-  // ---- 2. anisotropic diameter per group over the tent's space-time vertices ---
   {
-    const int nvert = npatch * (NS + 1) + 1;  // element vertices (repeats allowed) + top of V
+    const int nvert = npatch * (NS + 1) + 1;
     const long long npair = (long long)nvert * (nvert - 1) / 2;
     double hloc[kMaxGroups];
     for (int r = 0; r < kMaxGroups; ++r) hloc[r] = 0.0;
     for (long long pi = tid; pi < npair; pi += blockDim.x) {
-      // unrank pair (a, b), a < b
       int a = 0;
       long long rem = pi;
       while (rem >= nvert - 1 - a) {
@@ -229,141 +418,190 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
       double dx2 = 0.0;
       for (int d = 0; d < NS; ++d) dx2 += (xa[d] - xb[d]) * (xa[d] - xb[d]);
       const double dtt = ta - tbv;
-      for (int r = 0; r < m; ++r) hloc[r] = fmax(hloc[r], sqrt(dx2 + gc[r] * gc[r] * dtt * dtt));
+#pragma unroll
+      for (int r = 0; r < kMaxGroups; ++r)
+        if (r < m) hloc[r] = fmax(hloc[r], sqrt(dx2 + gc[r] * gc[r] * dtt * dtt));
     }
-    for (int r = 0; r < m; ++r) atomic_max_nonneg(&gh[r], hloc[r]);
+#pragma unroll
+    for (int r = 0; r < kMaxGroups; ++r)
+      if (r < m) atomic_max_nonneg(&gh[r], hloc[r]);
   }
-  // zero the system
-  for (int i = tid; i < S * lda; i += blockDim.x) A[i] = 0.0;
+  for (long long i = tid; i < (long long)S * lda; i += blockDim.x) A[i] = 0.0;
   for (int i = tid; i < kMaxGroups * NWP; i += blockDim.x) A0[i] = 0.0;
   __syncthreads();
 
-  const int parts = blockDim.x / PCH;
-  const int pt = tid % PCH;
-  const int part = tid / PCH;
-  double* PV = W2;                       // PCH x (NS+1): (th, xh_1..xh_n)
-  double* PD = W2 + PCH * (NS + 1);      // PCH x (NS+2): bottom data d_0..d_n, w*U_b
-  double* PWt = PD + PCH * (NS + 2);     // PCH weights
-
-  // ---- 3./4. top Gram, bottom right-hand side, U recovery rows ------------------
-  for (int i = 0; i < npatch; ++i) {
-    const double* R = EL + i * ELS;
-    const int r = (int)R[El<NS>::GRP];
-    const double ce = R[El<NS>::C];
-    const double hr = gh[r];
-    const int lV = (int)R[El<NS>::LV];
-    const int e = (int)R[El<NS>::E];
-    const double det = R[El<NS>::DET];
-    const double ic2 = 1.0 / (ce * ce);
-    double gn[NS], go[NS], gn2 = 0.0;
-    for (int d = 0; d < NS; ++d) {
-      gn[d] = R[El<NS>::GNEW + d];
-      go[d] = R[El<NS>::GOLD + d];
-      gn2 += gn[d] * gn[d];
-    }
-    const double sD = ic2 - gn2;  // > 0 on a space-like top facet
-    const double* st = P.state + (size_t)e * (NS + 2) * Q;
-    for (int q0 = 0; q0 < Q; q0 += PCH) {
-      // top points
-      if (tid < PCH) {
-        const int q = q0 + pt;
-        double x[NS], phi = 0.0, w = 0.0;
-        for (int d = 0; d < NS; ++d) x[d] = 0.0;
-        if (q < Q) {
-          const double* lam = P.lam_ref + (size_t)q * (NS + 1);
-          for (int k = 0; k <= NS; ++k) {
-            phi += lam[k] * R[El<NS>::TAU + k];
-            for (int d = 0; d < NS; ++d) x[d] += lam[k] * R[El<NS>::X + k * NS + d];
-          }
-          phi += lam[lV] * dt;
-          w = P.w_ref[q] * det;
-        }
-        PV[pt * (NS + 1)] = ce * (phi - tmid) / hr;
-        for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (x[d] - XV[d]) / hr;
-        PWt[pt] = w;
-        eval_mono(T, T.M1, mono, PCH, pt, PV + pt * (NS + 1));
-      }
-      __syncthreads();
-      {
-        const double w = PWt[pt];
-        const double sw = sqrt(w), swD = sqrt(w * sD);
-        for (int j = part; j < NW; j += parts) {
-          double f[NS + 1];
-          eval_fields<NS>(T, j, mono, PCH, pt, f);
-          const double v = ce * f[0];
-          double* row = W1 + (size_t)pt * (NS + 1) * NWP + j;
-          row[0] = swD * v;
-          for (int d = 0; d < NS; ++d) row[(1 + d) * NWP] = sw * (f[1 + d] - gn[d] * v);
-        }
-      }
-      __syncthreads();
-      acc_block(A, lda, r * NW, r * NW, W1, W1, PCH * (NS + 1), NWP, NW);
-      __syncthreads();
-      // bottom points
-      if (tid < PCH) {
-        const int q = q0 + pt;
-        double x[NS], phi = 0.0, w = 0.0;
-        for (int d = 0; d < NS; ++d) x[d] = 0.0;
-        double dd[NS + 2];
+  // ---- 2. top Gram (matrix cores), bottom right-hand side, U recovery rows --------
+  const int ntile_dim = (NW + 15) / 16;
+  const int ntiles = ntile_dim * (ntile_dim + 1) / 2;
+  const int padc = ntile_dim * 16 - NW;
+  // lower-triangular Gram tiles (I >= J) owned by this wave
+  int tI[TPW], tJ[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave * TPW + t;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+    tI[t] = tile < ntiles ? I : -1;
+    tJ[t] = tile - I * (I + 1) / 2;
+  }
+  const int LD2 = 2 * PCH;  // row stride of the monomial table (top points, then bottom points)
+  for (int r = 0; r < m; ++r) {
+    const double cr = gc[r], hr = gh[r];
+    const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
+    d4 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    double rhs_acc = 0.0, a0_acc = 0.0;    // column j = tid
+    double rhs_acc2 = 0.0, a0_acc2 = 0.0;  // column j = tid + blockDim.x
+    for (int f0 = 0; f0 < npts; f0 += PCH) {
+      const int nc = min(PCH, npts - f0);
+      // point set-up
+      for (int pt = tid; pt < PCH; pt += blockDim.x) {
+        double xt[NS], g[NS], dd[NS + 2];
+        double phi = tmid, pho = tmid, w = 0.0, sD = 0.0;
         for (int k = 0; k < NS + 2; ++k) dd[k] = 0.0;
-        if (q < Q) {
+        for (int d = 0; d < NS; ++d) {
+          xt[d] = XV[d];
+          g[d] = 0.0;
+        }
+        if (pt < nc) {
+          const int f = f0 + pt;
+          const int li = s_gel[s_goff[r] + f / Q];
+          const int q = f % Q;
+          const double* R = EL + li * ELS;
+          const int lV = (int)R[El<NS>::LV];
+          const int e = (int)R[El<NS>::E];
           const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+          pho = 0.0;
+          for (int d = 0; d < NS; ++d) xt[d] = 0.0;
           for (int k = 0; k <= NS; ++k) {
-            phi += lam[k] * R[El<NS>::TAU + k];
-            for (int d = 0; d < NS; ++d) x[d] += lam[k] * R[El<NS>::X + k * NS + d];
+            pho += lam[k] * R[El<NS>::TAU + k];
+            for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
           }
-          w = P.w_ref[q] * det;
+          phi = pho + lam[lV] * dt;
+          w = P.w_ref[q] * R[El<NS>::DET];
+          const double ic2 = 1.0 / (cr * cr);
+          double gn2 = 0.0;
+          for (int d = 0; d < NS; ++d) {
+            g[d] = R[El<NS>::GNEW + d];
+            gn2 += g[d] * g[d];
+          }
+          sD = ic2 - gn2;
+          const double* st = P.state + (size_t)e * (NS + 2) * Q;
           const double vb = st[q];
           double sg = 0.0;
-          for (int d = 0; d < NS; ++d) sg += st[(1 + d) * Q + q] * go[d];
+          for (int d = 0; d < NS; ++d) sg += st[(1 + d) * Q + q] * R[El<NS>::GOLD + d];
           dd[0] = w * (ic2 * vb - sg);
-          for (int d = 0; d < NS; ++d) dd[1 + d] = w * (st[(1 + d) * Q + q] - vb * go[d]);
+          for (int d = 0; d < NS; ++d) dd[1 + d] = w * (st[(1 + d) * Q + q] - vb * R[El<NS>::GOLD + d]);
           dd[NS + 1] = w * st[(NS + 1) * Q + q];
         }
-        PV[pt * (NS + 1)] = ce * (phi - tmid) / hr;
-        for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (x[d] - XV[d]) / hr;
+        PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
+        PV[(PCH + pt) * (NS + 1)] = cr * (pho - tmid) / hr;
+        for (int d = 0; d < NS; ++d) {
+          const double xh = (xt[d] - XV[d]) / hr;
+          PV[pt * (NS + 1) + 1 + d] = xh;
+          PV[(PCH + pt) * (NS + 1) + 1 + d] = xh;
+          PG[pt * NS + d] = g[d];
+        }
+        PW[pt] = w;
+        PS[pt] = sD;
         for (int k = 0; k < NS + 2; ++k) PD[pt * (NS + 2) + k] = dd[k];
-        PWt[pt] = w;
-        eval_mono(T, T.M, mono, PCH, pt, PV + pt * (NS + 1));
       }
       __syncthreads();
+      // powers and monomials of the top and bottom points
+      monomials<NS>(T, T.M, p, PV, POW, MT, LD2, 2 * PCH);
+      __syncthreads();
+      // fields: flat over (point, function)
+      for (int i = tid; i < PCH * NW; i += blockDim.x) {
+        const int pt = i % PCH, j = i / PCH;
+        const double w = PW[pt];
+        const double sw = sqrt(w), swD = sqrt(w * PS[pt]);
+        double f[NS + 1];
+        fields<NS>(T, j, MT, LD2, pt, f);
+        const double v = cr * f[0];
+        double* row = PSI + (size_t)pt * (NS + 1) * NWP + j;
+        row[0] = swD * v;
+        for (int d = 0; d < NS; ++d) row[(1 + d) * NWP] = sw * (f[1 + d] - PG[pt * NS + d] * v);
+        fields<NS>(T, j, MT, LD2, PCH + pt, f);
+        double accb = cr * f[0] * PD[pt * (NS + 2)];
+        for (int d = 0; d < NS; ++d) accb += f[1 + d] * PD[pt * (NS + 2) + 1 + d];
+        RB[pt * NWP + j] = accb;
+        UB[pt * NWP + j] = w * hr * ufield(T, j, MT, LD2, PCH + pt);
+      }
+      // zero the padding columns of PSI so the 16-wide tiles see zeros
+      for (int i = tid; i < PCH * (NS + 1) * padc; i += blockDim.x) {
+        const int row = i / padc, col = NW + i % padc;
+        PSI[row * NWP + col] = 0.0;
+      }
+      __syncthreads();
+      // Gram on the matrix cores: lane l of a k-step reads row 4 ks + l/16, column 16 I + l%16
       {
-        const double w = PWt[pt];
-        for (int j = part; j < NW; j += parts) {
-          double f[NS + 1];
-          eval_fields<NS>(T, j, mono, PCH, pt, f);
-          double acc = ce * f[0] * PD[pt * (NS + 2)];
-          for (int d = 0; d < NS; ++d) acc += f[1 + d] * PD[pt * (NS + 2) + 1 + d];
-          W1[pt * NWP + j] = acc;
-          W1[(PCH + pt) * NWP + j] = w * hr * eval_u(T, j, mono, PCH, pt);
+        const int nk = (nc * (NS + 1) + 3) / 4;
+        for (int ks = 0; ks < nk; ++ks) {
+          const double* rowp = PSI + (size_t)(ks * 4 + (lane >> 4)) * NWP + (lane & 15);
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+            if (tI[t] >= 0)
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowp[tI[t] * 16], rowp[tJ[t] * 16], acc[t], 0, 0, 0);
         }
       }
-      __syncthreads();
+      // right-hand side and recovery row: column sums over the chunk's points
       for (int j = tid; j < NW; j += blockDim.x) {
-        double acc = 0.0, acc0 = 0.0;
-        for (int k = 0; k < PCH; ++k) {
-          acc += W1[k * NWP + j];
-          acc0 += W1[(PCH + k) * NWP + j];
+        double s1 = 0.0, s2 = 0.0;
+        for (int pt = 0; pt < nc; ++pt) {
+          s1 += RB[pt * NWP + j];
+          s2 += UB[pt * NWP + j];
         }
-        A[(r * NW + j) * lda + S] += acc;
-        A0[r * NWP + j] += acc0;
+        if (j == tid) {
+          rhs_acc += s1;
+          a0_acc += s2;
+        } else {
+          rhs_acc2 += s1;
+          a0_acc2 += s2;
+        }
       }
       if (tid == blockDim.x - 1) {
         double sw = 0.0, su = 0.0;
-        for (int k = 0; k < PCH; ++k) {
-          sw += PWt[k];
-          su += PD[k * (NS + 2) + NS + 1];
+        for (int pt = 0; pt < nc; ++pt) {
+          sw += PW[pt];
+          su += PD[pt * (NS + 2) + NS + 1];
         }
         A00[r] += sw;
         r0[r] += su;
       }
       __syncthreads();
     }
+    // Gram tiles of block (r, r): element e of lane l is row l/16 + 4e, column l%16
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      if (tI[t] >= 0) {
+        const int I = tI[t], J = tJ[t];
+        const int j = J * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = I * 16 + (lane >> 4) + 4 * e;
+          if (i < NW && j < NW) {
+            A[(long long)(r * NW + i) * lda + r * NW + j] += acc[t][e];
+            if (I != J) A[(long long)(r * NW + j) * lda + r * NW + i] += acc[t][e];
+          }
+        }
+      }
+    }
+    if (tid < NW) {
+      A[(long long)(r * NW + tid) * lda + S] += rhs_acc;
+      A0[r * NWP + tid] += a0_acc;
+    }
+    if (tid + (int)blockDim.x < NW) {
+      A[(long long)(r * NW + tid + blockDim.x) * lda + S] += rhs_acc2;
+      A0[r * NWP + tid + blockDim.x] += a0_acc2;
+    }
+    __syncthreads();
   }
 
-  // ---- 5./6. time-like faces above facets containing V --------------------------
+  // ---- 3. time-like faces above facets containing V ---------------------------------
   const int nbf = P.vb_ptr[V + 1] - P.vb_ptr[V];
   const int nif = P.vi_ptr[V + 1] - P.vi_ptr[V];
+  double* F1 = W1;  // 4 x PCH rows of NWP: face values
   for (int f = 0; f < nbf + nif; ++f) {
     const bool dir = f < nbf;
     int e1, k1, e2 = -1;
@@ -376,8 +614,8 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
       k1 = q4[1];
       e2 = q4[2];
     }
-    // face simplex: (X_V, tb), (X_V, tt), (X_W, tau_W) for W in facet \ {V}
     if (tid == 0) {
+      // space-time simplex (X_V, tb), (X_V, tt), (X_W, tau_W) for W in facet \ {V}
       const int* vs = P.elems + (size_t)e1 * (NS + 1);
       double Pv[NS + 1][NS + 1];
       for (int d = 0; d < NS; ++d) {
@@ -394,7 +632,6 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
         Pv[c][NS] = P.tau[w];
         ++c;
       }
-      // Gram of the edge vectors E_i = P_i - P_0, i = 1..NS
       double E[NS][NS + 1], G[NS][NS];
       for (int i = 0; i < NS; ++i)
         for (int d = 0; d <= NS; ++d) E[i][d] = Pv[i + 1][d] - Pv[0][d];
@@ -420,7 +657,6 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
       for (int d = 0; d < NS; ++d) fsc[1 + d] = -gl[d] / nn;
       for (int i = 0; i <= NS; ++i)
         for (int d = 0; d <= NS; ++d) fsc[4 + i * (NS + 1) + d] = Pv[i][d];
-      // groups of the two sides
       int g1 = 0, g2 = 0;
       for (int i = 0; i < npatch; ++i) {
         const int e = (int)EL[i * ELS + El<NS>::E];
@@ -436,79 +672,84 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     const int ga = s_piv / 16, gb = s_piv % 16;
     const long long goff = P.bpt_off[tent] + (long long)f * Q;
     for (int q0 = 0; q0 < Q; q0 += PCH) {
+      const int nc = min(PCH, Q - q0);
       const int nside = dir ? 1 : 2;
       for (int side = 0; side < nside; ++side) {
         const int r = side == 0 ? ga : gb;
         const double cr = gc[r], hr = gh[r];
-        if (tid < PCH) {
-          const int q = q0 + pt;
+        for (int pt = tid; pt < PCH; pt += blockDim.x) {
           double y[NS + 1];
-          for (int d = 0; d <= NS; ++d) y[d] = 0.0;
+          for (int d = 0; d < NS; ++d) y[d] = XV[d];
+          y[NS] = tmid;
           double w = 0.0, g = 0.0;
-          if (q < Q) {
+          if (pt < nc) {
+            const int q = q0 + pt;
             const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+            for (int d = 0; d <= NS; ++d) y[d] = 0.0;
             for (int k = 0; k <= NS; ++k)
               for (int d = 0; d <= NS; ++d) y[d] += lam[k] * fsc[4 + k * (NS + 1) + d];
             w = P.w_ref[q] * meas;
             if (dir) g = P.gD[goff + q];
-          } else {
-            for (int d = 0; d < NS; ++d) y[d] = XV[d];
-            y[NS] = tmid;
           }
           PV[pt * (NS + 1)] = cr * (y[NS] - tmid) / hr;
           for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (y[d] - XV[d]) / hr;
-          PWt[pt] = w;
+          PW[pt] = w;
           PD[pt] = g;
-          eval_mono(T, T.M1, mono, PCH, pt, PV + pt * (NS + 1));
         }
         __syncthreads();
-        {
-          const double w = PWt[pt], sw = sqrt(w), g = PD[pt];
-          for (int j = part; j < NW; j += parts) {
-            double fl[NS + 1];
-            eval_fields<NS>(T, j, mono, PCH, pt, fl);
-            const double v = cr * fl[0];
-            double sn = 0.0;
-            for (int d = 0; d < NS; ++d) sn += fl[1 + d] * nrm[d];
-            if (dir) {
-              W1[pt * NWP + j] = sw * v;
-              W1[(PCH + pt) * NWP + j] = sw * (P.alpha * v + sn);
-              W1[(2 * PCH + pt) * NWP + j] = w * g * (P.alpha * v - sn);
-            } else {
-              W1[((2 * side) * PCH + pt) * NWP + j] = sw * v;
-              W1[((2 * side + 1) * PCH + pt) * NWP + j] = sw * sn;
-            }
+        monomials<NS>(T, T.M1, p, PV, POW, MT, PCH, PCH);
+        __syncthreads();
+        for (int i = tid; i < PCH * NW; i += blockDim.x) {
+          const int pt = i % PCH, j = i / PCH;
+          const double w = PW[pt], sw = sqrt(w), g = PD[pt];
+          double fl[NS + 1];
+          fields<NS>(T, j, MT, PCH, pt, fl);
+          const double v = cr * fl[0];
+          double sn = 0.0;
+          for (int d = 0; d < NS; ++d) sn += fl[1 + d] * nrm[d];
+          if (dir) {
+            F1[pt * NWP + j] = sw * v;
+            F1[(PCH + pt) * NWP + j] = sw * (P.alpha * v + sn);
+            F1[(2 * PCH + pt) * NWP + j] = w * g * (P.alpha * v - sn);
+          } else {
+            F1[((2 * side) * PCH + pt) * NWP + j] = sw * v;
+            F1[((2 * side + 1) * PCH + pt) * NWP + j] = sw * sn;
           }
         }
         __syncthreads();
       }
       if (dir) {
-        acc_block(A, lda, ga * NW, ga * NW, W1, W1 + PCH * NWP, PCH, NWP, NW);
+        for (int idx = tid; idx < NW * NW; idx += blockDim.x) {
+          const int ii = idx / NW, jj = idx % NW;
+          double acc = 0.0;
+          for (int k = 0; k < nc; ++k) acc += F1[k * NWP + ii] * F1[(PCH + k) * NWP + jj];
+          A[(long long)(ga * NW + ii) * lda + ga * NW + jj] += acc;
+        }
         for (int j = tid; j < NW; j += blockDim.x) {
           double acc = 0.0;
-          for (int k = 0; k < PCH; ++k) acc += W1[(2 * PCH + k) * NWP + j];
-          A[(ga * NW + j) * lda + S] += acc;
+          for (int k = 0; k < nc; ++k) acc += F1[(2 * PCH + k) * NWP + j];
+          A[(long long)(ga * NW + j) * lda + S] += acc;
         }
       } else {
         // test in group b (sign sb), trial in group a (sign sa):
         // w_i (alpha sa sb v_j + sb/2 s_j.n) + (tau_i.n)(sb/2 v_j + beta sa sb s_j.n)
         for (int blk = 0; blk < 4; ++blk) {
-          const int sa_i = blk / 2, sb_i = blk % 2;  // side index of trial / test
+          const int sa_i = blk / 2, sb_i = blk % 2;
           const double sa = sa_i ? -1.0 : 1.0, sb = sb_i ? -1.0 : 1.0;
           const int gA = sa_i ? gb : ga, gB = sb_i ? gb : ga;
-          const double* Va = W1 + (2 * sa_i) * PCH * NWP;
-          const double* Na = W1 + (2 * sa_i + 1) * PCH * NWP;
-          const double* Vb = W1 + (2 * sb_i) * PCH * NWP;
-          const double* Nb = W1 + (2 * sb_i + 1) * PCH * NWP;
+          const double* Va = F1 + (2 * sa_i) * PCH * NWP;
+          const double* Na = F1 + (2 * sa_i + 1) * PCH * NWP;
+          const double* Vb = F1 + (2 * sb_i) * PCH * NWP;
+          const double* Nb = F1 + (2 * sb_i + 1) * PCH * NWP;
           for (int idx = tid; idx < NW * NW; idx += blockDim.x) {
             const int ii = idx / NW, jj = idx % NW;
             double acc = 0.0;
-            for (int k = 0; k < PCH; ++k) {
+            for (int k = 0; k < nc; ++k) {
               const double va = Va[k * NWP + jj], na = Na[k * NWP + jj];
               acc += Vb[k * NWP + ii] * (P.alpha * sa * sb * va + 0.5 * sb * na) +
                      Nb[k * NWP + ii] * (0.5 * sb * va + P.beta * sa * sb * na);
             }
-            A[(gB * NW + ii) * lda + gA * NW + jj] += acc;
+            A[(long long)(gB * NW + ii) * lda + gA * NW + jj] += acc;
           }
         }
       }
@@ -516,64 +757,22 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     }
   }
 
-  // ---- 7. LU with partial pivoting on the augmented matrix -----------------------
-  for (int k = 0; k < S; ++k) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = S;
-      for (int rr = k + tid; rr < S; rr += 64) {
-        const double v = fabs(A[rr * lda + k]);
-        if (v > best) {
-          best = v;
-          bi = rr;
-        }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_down(best, off, 64);
-        const int oi = __shfl_down(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (tid == 0) s_piv = bi;
-    }
+  // ---- 4. LU with partial pivoting, back substitution, U constants ----------------
+  bool ok;
+  if (S <= 64 && L.A_in_lds) {
+    bool w_ok = true;
+    if (wave == 0) w_ok = wave_lu_solve(A, (int)lda, S, xs);
+    if (wave == 0 && lane == 0 && !w_ok) s_err = kStatSingular;
     __syncthreads();
-    const int pr = s_piv;
-    if (pr != k)
-      for (int j = k + tid; j <= S; j += blockDim.x) {
-        const double t = A[k * lda + j];
-        A[k * lda + j] = A[pr * lda + j];
-        A[pr * lda + j] = t;
-      }
-    __syncthreads();
-    const double piv = A[k * lda + k];
-    if (piv == 0.0) {
-      if (tid == 0) s_err = kStatSingular;
-      break;
-    }
-    for (int i = k + 1 + tid; i < S; i += blockDim.x) A[i * lda + k] /= piv;
-    __syncthreads();
-    const int nr = S - k - 1, nc = S - k;
-    for (int idx = tid; idx < nr * nc; idx += blockDim.x) {
-      const int i = k + 1 + idx / nc, j = k + 1 + idx % nc;
-      A[i * lda + j] -= A[i * lda + k] * A[k * lda + j];
-    }
+    ok = s_err == 0;
+  } else {
+    ok = block_lu_solve(A, lda, S, xs, &s_piv);
     __syncthreads();
   }
-  __syncthreads();
-  if (s_err) {
-    if (tid == 0) atomicOr(P.status, s_err);
+  if (!ok) {
+    if (tid == 0) atomicOr(P.status, kStatSingular);
     return;
   }
-  for (int k = S - 1; k >= 0; --k) {
-    if (tid == 0) xs[k] = A[k * lda + S] / A[k * lda + k];
-    __syncthreads();
-    const double xk = xs[k];
-    for (int i = tid; i < k; i += blockDim.x) A[i * lda + S] -= A[i * lda + k] * xk;
-    __syncthreads();
-  }
-  // U constants (Sec. 5): mean of U over the bottom matches the incoming mean
   if (tid < m) {
     double s = r0[tid];
     for (int j = 0; j < NW; ++j) s -= A0[tid * NWP + j] * xs[tid * NW + j];
@@ -581,10 +780,11 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
   }
   __syncthreads();
 
-  // ---- 8. top values overwrite the stored values -------------------------------
-  double* cm = W1;                 // (NS+1) x M1: field coefficients contracted with x
+  // ---- 5. top values overwrite the stored values -----------------------------------
+  double* cm = W1;                    // (NS+1) x M1: field coefficients contracted with x
   double* cu = W1 + (NS + 1) * T.M1;  // M: U coefficients contracted with x
   for (int r = 0; r < m; ++r) {
+    const double cr = gc[r], hr = gh[r];
     for (int i = tid; i < (NS + 1) * T.M1 + T.M; i += blockDim.x) cm[i] = 0.0;
     __syncthreads();
     if (tid <= NS) {
@@ -596,90 +796,129 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
       }
     } else if (tid == NS + 1) {
       for (int j = 0; j < NW; ++j) {
-        const double xj = xs[r * NW + j] * gh[r];
+        const double xj = xs[r * NW + j] * hr;
         for (int e = T.u_ptr[j]; e < T.u_ptr[j + 1]; ++e) cu[T.u_idx[e]] += T.u_coef[e] * xj;
       }
     }
     __syncthreads();
-    const double cr = gc[r], hr = gh[r];
-    for (int i = 0; i < npatch; ++i) {
-      const double* R = EL + i * ELS;
-      if ((int)R[El<NS>::GRP] != r) continue;
-      const int lV = (int)R[El<NS>::LV];
-      const int e = (int)R[El<NS>::E];
-      double* st = P.state + (size_t)e * (NS + 2) * Q;
-      for (int q0 = 0; q0 < Q; q0 += PCH) {
-        if (tid < PCH) {
-          const int q = q0 + pt;
-          double x[NS], phi = 0.0;
-          for (int d = 0; d < NS; ++d) x[d] = 0.0;
-          if (q < Q) {
-            const double* lam = P.lam_ref + (size_t)q * (NS + 1);
-            for (int k = 0; k <= NS; ++k) {
-              phi += lam[k] * R[El<NS>::TAU + k];
-              for (int d = 0; d < NS; ++d) x[d] += lam[k] * R[El<NS>::X + k * NS + d];
-            }
-            phi += lam[lV] * dt;
+    const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
+    for (int f0 = 0; f0 < npts; f0 += LD2) {
+      const int nc = min(LD2, npts - f0);
+      for (int pt = tid; pt < LD2; pt += blockDim.x) {
+        double xt[NS], phi = tmid;
+        for (int d = 0; d < NS; ++d) xt[d] = XV[d];
+        if (pt < nc) {
+          const int f = f0 + pt;
+          const int li = s_gel[s_goff[r] + f / Q];
+          const int q = f % Q;
+          const double* R = EL + li * ELS;
+          const int lV = (int)R[El<NS>::LV];
+          const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+          phi = 0.0;
+          for (int d = 0; d < NS; ++d) xt[d] = 0.0;
+          for (int k = 0; k <= NS; ++k) {
+            phi += lam[k] * R[El<NS>::TAU + k];
+            for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
           }
-          PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
-          for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (x[d] - XV[d]) / hr;
-          eval_mono(T, T.M, mono, PCH, pt, PV + pt * (NS + 1));
-          if (q < Q) {
-            double out[NS + 2];
-            for (int comp = 0; comp <= NS; ++comp) {
-              double acc = 0.0;
-              for (int k = 0; k < T.M1; ++k) acc += cm[comp * T.M1 + k] * mono[k * PCH + pt];
-              out[comp] = acc;
-            }
-            out[0] *= cr;
-            double u = a0[r];
-            for (int k = 0; k < T.M; ++k) u += cu[k] * mono[k * PCH + pt];
-            out[NS + 1] = u;
-            bool bad = false;
-            for (int comp = 0; comp < NS + 2; ++comp) {
-              st[comp * Q + q] = out[comp];
-              bad = bad || !isfinite(out[comp]);
-            }
-            if (bad) atomicOr(P.status, kStatNan);
-          }
+          phi += lam[lV] * dt;
         }
+        PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
+        for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (xt[d] - XV[d]) / hr;
       }
+      __syncthreads();
+      monomials<NS>(T, T.M, p, PV, POW, MT, LD2, LD2);
+      __syncthreads();
+      for (int i = tid; i < nc * (NS + 2); i += blockDim.x) {
+        const int pt = i % nc, comp = i / nc;
+        double acc = 0.0;
+        if (comp <= NS) {
+          for (int k = 0; k < T.M1; ++k) acc += cm[comp * T.M1 + k] * MT[k * LD2 + pt];
+          if (comp == 0) acc *= cr;
+        } else {
+          acc = a0[r];
+          for (int k = 0; k < T.M; ++k) acc += cu[k] * MT[k * LD2 + pt];
+        }
+        const int f = f0 + pt;
+        const int li = s_gel[s_goff[r] + f / Q];
+        const int q = f % Q;
+        const int e = (int)EL[li * ELS + El<NS>::E];
+        P.state[((size_t)e * (NS + 2) + comp) * Q + q] = acc;
+        if (!isfinite(acc)) atomicOr(P.status, kStatNan);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (tid == 0) P.tau[V] = tt;
 }
 
-int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, void* stream_) {
-  hipStream_t stream = (hipStream_t)stream_;
-  if (count <= 0) return 0;
+namespace {
+
+template <int NS>
+hipError_t launch_ns(const KParams& P, const LdsPlan& L, int t0, int count, hipStream_t stream) {
   dim3 grid(count), block(kBlock);
   size_t shm = (size_t)L.total * sizeof(double);
-  switch (P.n) {
+  switch (L.TPW) {
     case 1:
-      hipLaunchKernelGGL(tent_layer_kernel<1>, grid, block, shm, stream, P, L, t0);
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 1>), grid, block, shm, stream, P, L, t0);
       break;
     case 2:
-      hipLaunchKernelGGL(tent_layer_kernel<2>, grid, block, shm, stream, P, L, t0);
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 2>), grid, block, shm, stream, P, L, t0);
+      break;
+    case 4:
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 4>), grid, block, shm, stream, P, L, t0);
+      break;
+    case 8:
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 8>), grid, block, shm, stream, P, L, t0);
       break;
     default:
-      hipLaunchKernelGGL(tent_layer_kernel<3>, grid, block, shm, stream, P, L, t0);
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 16>), grid, block, shm, stream, P, L, t0);
       break;
   }
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return hipGetLastError();
+}
+
+template <int NS>
+hipError_t smem_ns(size_t bytes) {
+  const hipFuncAttribute a = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 1>, a, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 2>, a, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 4>, a, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 8>, a, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 16>, a, (int)bytes);
+  return e;
+}
+
+}  // namespace
+
+int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, void* stream_) {
+  if (count <= 0) return 0;
+  hipStream_t stream = (hipStream_t)stream_;
+  hipError_t e;
+  switch (P.n) {
+    case 1:
+      e = launch_ns<1>(P, L, t0, count, stream);
+      break;
+    case 2:
+      e = launch_ns<2>(P, L, t0, count, stream);
+      break;
+    default:
+      e = launch_ns<3>(P, L, t0, count, stream);
+      break;
+  }
+  return e == hipSuccess ? 0 : -1;
 }
 
 int set_kernel_smem_limit(int n, size_t bytes) {
   hipError_t e;
   switch (n) {
     case 1:
-      e = hipFuncSetAttribute((const void*)tent_layer_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      e = smem_ns<1>(bytes);
       break;
     case 2:
-      e = hipFuncSetAttribute((const void*)tent_layer_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      e = smem_ns<2>(bytes);
       break;
     default:
-      e = hipFuncSetAttribute((const void*)tent_layer_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      e = smem_ns<3>(bytes);
       break;
   }
   return e == hipSuccess ? 0 : -1;

@@ -34,6 +34,9 @@ CASES = {
     "2d_interface_p3": lambda: (C.cfg4_interface_2d(m=9, p=3), None, None),
     "3d_p3_b": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="b"), None, None),
     "3d_p2_a_groups": lambda: (C.cfg5_cube_3d(m=3, p=2, variant="a", regions=3), None, None),
+    "2d_p8_m4": lambda: (C.cfg2_plane_2d(m=4, p=8), None, None),
+    "3d_p5_b": lambda: (C.cfg5_cube_3d(m=2, p=5, variant="b"), None, None),
+    "3d_p3_a_8groups_global_system": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="a", regions=2), None, None),
 }
 
 
@@ -41,7 +44,7 @@ CASES = {
 def test_full_run_matches_oracle(name):
     pr, field, q = CASES[name]()
     if pr.n == 3:
-        pr.T = 0.25
+        pr.T = 0.25 if pr.p <= 3 else 0.1
     say(f"[gpu parity] {name}: n={pr.n} p={pr.p} ne={len(pr.elems)}")
     o = oracle_for(pr, field, q=q)
     o.run()
