@@ -58,7 +58,8 @@ struct tdg_ctx {
   std::vector<double> hf64;
   std::vector<int> hi32;
   struct TabOff {
-    size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx;  // i32
+    size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx, ue_ptr, ue_idx, tr_ptr, tr_j;  // i32
+    size_t ue_coef, tr_coef;                                                           // f64
     size_t fo_coef, u_coef, fo_coef32;                 // f64 (fo_coef32: floats packed two per double)
   } toff[kMaxP + 1];
   size_t o_coords, o_c, o_grad, o_det, o_lam, o_w, o_tb, o_tt, o_bpt;         // f64
@@ -114,10 +115,13 @@ int plan_lds(tdg_ctx* X) {
   L.M = Tm.M;
   L.maxpatch = maxpatch;
   L.ELS = el_size(n);
-  const int nfp = Tm.NW * (n + 1) + 1, nnz = (int)Tm.fo_idx.size(), nup = Tm.NW + 1, unz = (int)Tm.u_idx.size();
-  const int nex = Tm.M * (n + 1);
-  L.tab_int_dbl = (nfp + nnz + nup + unz + nex + 1) / 2;
-  const int tab_dbl = L.tab_int_dbl + nnz + unz;
+  L.maxfaces = 0;
+  for (int v = 0; v < X->topo.nv; ++v) L.maxfaces = std::max(L.maxfaces, X->topo.vb_ptr[v + 1] - X->topo.vb_ptr[v]);
+  if (L.maxfaces > kMaxFaces) return fail(TDG_EINVAL, "too many boundary facets at one vertex");
+  const int nue = Tm.ue_ptr.back(), ntr = (int)Tm.tr_j.size();
+  const int nint = (Tm.NW + 1) + nue * (n + 2) + ((n + 2) * Tm.M + 1) + ntr + Tm.M * (n + 1);
+  L.tab_int_dbl = (nint + 1) / 2;
+  const int tab_dbl = L.tab_int_dbl + nue * (n + 2) + ntr;
   struct Choice {
     bool a, t;
     int min_pch;
@@ -141,7 +145,8 @@ int plan_lds(tdg_ctx* X) {
       L.off_pt = take((long long)pch * (2 * (n + 1) + 1 + (n + 2) + n + 1));
       L.off_pow = take(2LL * pch * (n + 1) * (X->opts.p_max + 1));
       L.off_mono = take((long long)Tm.M * 2 * pch);
-      L.off_W1 = take(std::max<long long>((long long)pch * (n + 3) * L.NWP, (n + 1) * Tm.M1 + Tm.M));
+      L.off_W1 = take(std::max<long long>((long long)pch * (n + 3) * L.NWP, (long long)(n + 2) * Tm.M));
+      L.off_fg = take((long long)std::max(L.maxfaces, 1) * (2 + n + (n + 1) * (n + 1)));
       L.off_tab = ch.t ? take(tab_dbl) : 0;
       L.off_A = ch.a ? take((long long)L.S * L.lda) : 0;
       L.total = off;
@@ -302,6 +307,12 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     o.fo_idx = push(X->hi32, tb.fo_idx.data(), tb.fo_idx.size());
     o.u_ptr = push(X->hi32, tb.u_ptr.data(), tb.u_ptr.size());
     o.u_idx = push(X->hi32, tb.u_idx.data(), tb.u_idx.size());
+    o.ue_ptr = push(X->hi32, tb.ue_ptr.data(), tb.ue_ptr.size());
+    o.ue_idx = push(X->hi32, tb.ue_idx.data(), tb.ue_idx.size());
+    o.tr_ptr = push(X->hi32, tb.tr_ptr.data(), tb.tr_ptr.size());
+    o.tr_j = push(X->hi32, tb.tr_j.data(), tb.tr_j.size());
+    o.ue_coef = push(X->hf64, tb.ue_coef.data(), tb.ue_coef.size());
+    o.tr_coef = push(X->hf64, tb.tr_coef.data(), tb.tr_coef.size());
     o.fo_coef = push(X->hf64, tb.fo_coef.data(), tb.fo_coef.size());
     o.u_coef = push(X->hf64, tb.u_coef.data(), tb.u_coef.size());
     std::vector<float> f32(tb.fo_coef.begin(), tb.fo_coef.end());
@@ -435,6 +446,14 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
     D.M1 = tb.M1;
     D.fo_nnz = (int)tb.fo_idx.size();
     D.u_nnz = (int)tb.u_idx.size();
+    D.ue_n = tb.ue_ptr.back();
+    D.tr_n = (int)tb.tr_j.size();
+    D.ue_ptr = I + o.ue_ptr;
+    D.ue_idx = I + o.ue_idx;
+    D.ue_coef = F + o.ue_coef;
+    D.tr_ptr = I + o.tr_ptr;
+    D.tr_j = I + o.tr_j;
+    D.tr_coef = F + o.tr_coef;
     D.parent = I + o.parent;
     D.var = I + o.var;
     D.expo = I + o.expo;

@@ -12,6 +12,7 @@ namespace tdg {
 constexpr int kMaxP = 10;        // highest degree of U^p with tables
 constexpr int kMaxGroups = 8;    // speed groups inside one tent (Sec. 4.2)
 constexpr int kMaxPatch = 64;    // elements in one vertex patch
+constexpr int kMaxFaces = 64;    // Dirichlet facets containing one vertex
 constexpr int kBlock = 256;      // threads per workgroup of the tent kernels
 
 // Sparse tables of the Trefftz basis of U^p (c = 1) over the monomials
@@ -22,7 +23,18 @@ constexpr int kBlock = 256;      // threads per workgroup of the tent kernels
 // for the non-constant functions j = 0..NW-1 (basis functions 1..N-1).
 // U table: CSR over rows j (basis function j+1).
 struct TableDesc {
-  int p, NW, M, M1, fo_nnz, u_nnz;
+  int p, NW, M, M1, fo_nnz, u_nnz, ue_n, tr_n;
+  // entry form: entries of basis function j+1 are ue_ptr[j]..ue_ptr[j+1]-1; entry e
+  // holds (n+2) pairs (monomial index, coefficient) for U, v = dU/dt and
+  // sigma_m = -dU/dx_m: ue_idx[e*(n+2)+s], ue_coef[e*(n+2)+s] (coefficient 0 if absent)
+  const int* ue_ptr;
+  const int* ue_idx;
+  const double* ue_coef;
+  // transposed form for the write-back: row comp*M + mono (comp 0 = v, 1..n = sigma,
+  // n+1 = U) lists (function j, coefficient): tr_ptr, tr_j, tr_coef
+  const int* tr_ptr;
+  const int* tr_j;
+  const double* tr_coef;
   const int* parent;
   const int* var;
   const int* expo;  // M*(n+1) exponents (k, alpha) of each monomial
@@ -96,7 +108,8 @@ struct LdsPlan {
   int A_in_lds;  // 1: system in LDS; 0: in the global scratch slot of the workgroup
   int tab_in_lds;
   int tab_int_dbl;  // doubles occupied by the integer part of a staged table
-  int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, total;
+  int maxfaces;  // Dirichlet facets containing one vertex, at most
+  int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, off_fg, total;
 };
 
 int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, void* stream);
@@ -137,6 +150,10 @@ struct Table {
   std::vector<double> fo_coef;
   std::vector<int> u_ptr, u_idx;
   std::vector<double> u_coef;
+  std::vector<int> ue_ptr, ue_idx;
+  std::vector<double> ue_coef;
+  std::vector<int> tr_ptr, tr_j;
+  std::vector<double> tr_coef;
 };
 Table build_table(int n, int p);
 

@@ -18,8 +18,8 @@
 //          U recovery row (Sec. 5): the mean of U over the bottom facets.
 //   3. Dirichlet faces: A_ij += w v_i (alpha v_j + s_j.n), rhs_i += w g_D (alpha v_i - s_i.n);
 //      speed interfaces: centred fluxes with penalties (Sec. 4.2).
-//   4. LU with partial pivoting (one wave for systems up to 64 unknowns, the
-//      whole workgroup otherwise), back substitution, U constants.
+//   4. LU: one wave with rows in registers and diagonal pivots for systems up
+//      to 32 unknowns; the whole workgroup with partial pivoting otherwise, back substitution, U constants.
 //   5. (v, sigma, U) at the top points overwrite the stored values; tau_V = t_top.
 #include <hip/hip_runtime.h>
 
@@ -57,14 +57,14 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Table of one degree, possibly staged in LDS.
+// Table of one degree, possibly staged in LDS (see TableDesc).
 struct Tab {
-  const int* fo_ptr;
-  const int* fo_idx;
-  const double* fo_coef;
-  const int* u_ptr;
-  const int* u_idx;
-  const double* u_coef;
+  const int* ue_ptr;
+  const int* ue_idx;
+  const double* ue_coef;
+  const int* tr_ptr;
+  const int* tr_j;
+  const double* tr_coef;
   const int* expo;  // M*(NS+1) exponents (k, alpha)
   int NW, M, M1;
 };
@@ -98,60 +98,66 @@ __device__ inline void monomials(const Tab& T, int count, int p, const double* v
   }
 }
 
-template <int NS>
-__device__ inline void fields(const Tab& T, int j, const double* mono, int ld, int pt, double* out) {
+// vhat = dUhat/dth, sigmahat = -grad Uhat (f[0..NS]) and optionally Uhat of
+// basis function j+1 at point pt, one pass over the terms of Uhat.
+template <int NS, bool WITH_U>
+__device__ inline void eval_j(const Tab& T, int j, const double* mono, int ld, int pt, double* f, double* u) {
+  double acc[NS + 2];
 #pragma unroll
-  for (int comp = 0; comp <= NS; ++comp) {
-    const int r = j * (NS + 1) + comp;
-    double acc = 0.0;
-    for (int e = T.fo_ptr[r]; e < T.fo_ptr[r + 1]; ++e) acc += T.fo_coef[e] * mono[T.fo_idx[e] * ld + pt];
-    out[comp] = acc;
+  for (int s = 0; s < NS + 2; ++s) acc[s] = 0.0;
+  const int e1 = T.ue_ptr[j + 1];
+  for (int e = T.ue_ptr[j]; e < e1; ++e) {
+    const int* ix = T.ue_idx + e * (NS + 2);
+    const double* cf = T.ue_coef + e * (NS + 2);
+#pragma unroll
+    for (int s = WITH_U ? 0 : 1; s < NS + 2; ++s) acc[s] += cf[s] * mono[ix[s] * ld + pt];
   }
+#pragma unroll
+  for (int s = 0; s <= NS; ++s) f[s] = acc[1 + s];
+  if (WITH_U) *u = acc[0];
 }
 
-__device__ inline double ufield(const Tab& T, int j, const double* mono, int ld, int pt) {
-  double acc = 0.0;
-  for (int e = T.u_ptr[j]; e < T.u_ptr[j + 1]; ++e) acc += T.u_coef[e] * mono[T.u_idx[e] * ld + pt];
-  return acc;
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// LU with partial pivoting of the augmented S x (S+1) matrix by one wave
-// (S <= 64): lane i owns row i.  Returns false on a zero pivot.
-__device__ inline bool wave_lu_solve(double* A, int lda, int S, double* x) {
+// LU without row exchanges of the augmented S x (S+1) matrix (S <= SMAX <= 64)
+// by one wave, rows in registers: lane i holds row i; row k is broadcast with
+// readlane.  The local matrices have a positive definite symmetric part
+// (u^T A u = 1/2 B_top(u,u) + 1/2 B_bot(u,u) + penalty terms > 0 for Trefftz
+// u, from eq. 4.1 and the divergence theorem), so every leading minor is
+// nonzero and elimination with diagonal pivots is stable.  Returns false on a
+// zero pivot.
+template <int SMAX>
+__device__ inline bool wave_lu_regs(const double* A, int lda, int S, double* x) {
   const int lane = threadIdx.x & 63;
-  for (int k = 0; k < S; ++k) {
-    double v = (lane >= k && lane < S) ? fabs(A[lane * lda + k]) : -1.0;
-    int bi = lane;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ov > v || (ov == v && oi < bi)) {
-        v = ov;
-        bi = oi;
-      }
+  double r[SMAX + 1];
+#pragma unroll
+  for (int j = 0; j < SMAX; ++j) r[j] = (lane < S && j < S) ? A[lane * lda + j] : 0.0;
+  r[SMAX] = lane < S ? A[lane * lda + S] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < SMAX; ++k) {
+    if (k < S) {
+      const double pk = readlane_d(r[k], k);
+      if (pk == 0.0) ok = false;
+      const double l = lane > k ? r[k] / pk : 0.0;
+#pragma unroll
+      for (int j = k + 1; j <= SMAX; ++j)
+        if (j < S || j == SMAX) r[j] -= l * readlane_d(r[j], k);
     }
-    if (bi != k) {
-      for (int j = k + lane; j <= S; j += 64) {
-        const double t = A[k * lda + j];
-        A[k * lda + j] = A[bi * lda + j];
-        A[bi * lda + j] = t;
-      }
-    }
-    wave_sync();
-    const double piv = A[k * lda + k];
-    if (piv == 0.0) return false;
-    if (lane > k && lane < S) {
-      const double l = A[lane * lda + k] / piv;
-      A[lane * lda + k] = l;
-      for (int j = k + 1; j <= S; ++j) A[lane * lda + j] -= l * A[k * lda + j];
-    }
-    wave_sync();
   }
-  for (int k = S - 1; k >= 0; --k) {
-    const double xk = A[k * lda + S] / A[k * lda + k];
-    if (lane == 0) x[k] = xk;
-    if (lane < k) A[lane * lda + S] -= A[lane * lda + k] * xk;
-    wave_sync();
+  if (!ok) return false;
+#pragma unroll
+  for (int k = SMAX - 1; k >= 0; --k) {
+    if (k < S) {
+      const double xk = readlane_d(r[SMAX], k) / readlane_d(r[k], k);
+      if (lane == 0) x[k] = xk;
+      if (lane < k) r[SMAX] -= r[k] * xk;
+    }
   }
   return true;
 }
@@ -218,6 +224,7 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
   extern __shared__ double lds[];
   __shared__ int s_m, s_piv, s_err, s_goff[kMaxGroups + 1];
   __shared__ int s_gel[kMaxPatch];
+  __shared__ int s_fl[kMaxFaces], s_foff[kMaxGroups + 1];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int tent = t0 + blockIdx.x;
@@ -270,41 +277,41 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     T.M = D.M;
     T.M1 = D.M1;
     if (L.tab_in_lds) {
+      const int nue = D.ue_n, ntr = D.tr_n, nrow = (NS + 2) * D.M;
       int* ti = reinterpret_cast<int*>(lds + L.off_tab);
       double* td = lds + L.off_tab + L.tab_int_dbl;
-      const int nfp = D.NW * (NS + 1) + 1, nnz = D.fo_nnz, nup = D.NW + 1, unz = D.u_nnz, nex = D.M * (NS + 1);
-      int* t_fp = ti;
-      int* t_fi = t_fp + nfp;
-      int* t_up = t_fi + nnz;
-      int* t_ui = t_up + nup;
-      int* t_ex = t_ui + unz;
-      double* t_fc = td;
-      double* t_uc = td + nnz;
-      for (int i = tid; i < nfp; i += blockDim.x) t_fp[i] = D.fo_ptr[i];
-      for (int i = tid; i < nnz; i += blockDim.x) {
-        t_fi[i] = D.fo_idx[i];
-        t_fc[i] = D.fo_coef[i];
+      int* t_up = ti;
+      int* t_ui = t_up + (D.NW + 1);
+      int* t_tp = t_ui + nue * (NS + 2);
+      int* t_tj = t_tp + nrow + 1;
+      int* t_ex = t_tj + ntr;
+      double* t_uc = td;
+      double* t_tc = td + nue * (NS + 2);
+      for (int i = tid; i <= D.NW; i += blockDim.x) t_up[i] = D.ue_ptr[i];
+      for (int i = tid; i < nue * (NS + 2); i += blockDim.x) {
+        t_ui[i] = D.ue_idx[i];
+        t_uc[i] = D.ue_coef[i];
       }
-      for (int i = tid; i < nup; i += blockDim.x) t_up[i] = D.u_ptr[i];
-      for (int i = tid; i < unz; i += blockDim.x) {
-        t_ui[i] = D.u_idx[i];
-        t_uc[i] = D.u_coef[i];
+      for (int i = tid; i <= nrow; i += blockDim.x) t_tp[i] = D.tr_ptr[i];
+      for (int i = tid; i < ntr; i += blockDim.x) {
+        t_tj[i] = D.tr_j[i];
+        t_tc[i] = D.tr_coef[i];
       }
-      for (int i = tid; i < nex; i += blockDim.x) t_ex[i] = D.expo[i];
-      T.fo_ptr = t_fp;
-      T.fo_idx = t_fi;
-      T.fo_coef = t_fc;
-      T.u_ptr = t_up;
-      T.u_idx = t_ui;
-      T.u_coef = t_uc;
+      for (int i = tid; i < D.M * (NS + 1); i += blockDim.x) t_ex[i] = D.expo[i];
+      T.ue_ptr = t_up;
+      T.ue_idx = t_ui;
+      T.ue_coef = t_uc;
+      T.tr_ptr = t_tp;
+      T.tr_j = t_tj;
+      T.tr_coef = t_tc;
       T.expo = t_ex;
     } else {
-      T.fo_ptr = D.fo_ptr;
-      T.fo_idx = D.fo_idx;
-      T.fo_coef = D.fo_coef;
-      T.u_ptr = D.u_ptr;
-      T.u_idx = D.u_idx;
-      T.u_coef = D.u_coef;
+      T.ue_ptr = D.ue_ptr;
+      T.ue_idx = D.ue_idx;
+      T.ue_coef = D.ue_coef;
+      T.tr_ptr = D.tr_ptr;
+      T.tr_j = D.tr_j;
+      T.tr_coef = D.tr_coef;
       T.expo = D.expo;
     }
   }
@@ -516,17 +523,17 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
         const int pt = i % PCH, j = i / PCH;
         const double w = PW[pt];
         const double sw = sqrt(w), swD = sqrt(w * PS[pt]);
-        double f[NS + 1];
-        fields<NS>(T, j, MT, LD2, pt, f);
+        double f[NS + 1], fb[NS + 1], ub;
+        eval_j<NS, false>(T, j, MT, LD2, pt, f, &ub);
+        eval_j<NS, true>(T, j, MT, LD2, PCH + pt, fb, &ub);
         const double v = cr * f[0];
         double* row = PSI + (size_t)pt * (NS + 1) * NWP + j;
         row[0] = swD * v;
         for (int d = 0; d < NS; ++d) row[(1 + d) * NWP] = sw * (f[1 + d] - PG[pt * NS + d] * v);
-        fields<NS>(T, j, MT, LD2, PCH + pt, f);
-        double accb = cr * f[0] * PD[pt * (NS + 2)];
-        for (int d = 0; d < NS; ++d) accb += f[1 + d] * PD[pt * (NS + 2) + 1 + d];
+        double accb = cr * fb[0] * PD[pt * (NS + 2)];
+        for (int d = 0; d < NS; ++d) accb += fb[1 + d] * PD[pt * (NS + 2) + 1 + d];
         RB[pt * NWP + j] = accb;
-        UB[pt * NWP + j] = w * hr * ufield(T, j, MT, LD2, PCH + pt);
+        UB[pt * NWP + j] = w * hr * ub;
       }
       // zero the padding columns of PSI so the 16-wide tiles see zeros
       for (int i = tid; i < PCH * (NS + 1) * padc; i += blockDim.x) {
@@ -602,8 +609,165 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
   const int nbf = P.vb_ptr[V + 1] - P.vb_ptr[V];
   const int nif = P.vi_ptr[V + 1] - P.vi_ptr[V];
   double* F1 = W1;  // 4 x PCH rows of NWP: face values
-  for (int f = 0; f < nbf + nif; ++f) {
-    const bool dir = f < nbf;
+  if (nbf > L.maxfaces) {
+    if (tid == 0) atomicOr(P.status, kStatSize);
+    return;
+  }
+  // 3a. Dirichlet faces: geometry of every face, then all face points of a
+  //     speed group in one chunked pass
+  constexpr int FGS = 2 + NS + (NS + 1) * (NS + 1);  // measure, group, normal, simplex vertices
+  double* FG = lds + L.off_fg;
+  for (int f = tid; f < nbf; f += blockDim.x) {
+    const int e1 = P.vb[2 * (P.vb_ptr[V] + f)];
+    const int k1 = P.vb[2 * (P.vb_ptr[V] + f) + 1];
+    double* G0 = FG + f * FGS;
+    const int* vs = P.elems + (size_t)e1 * (NS + 1);
+    double Pv[NS + 1][NS + 1];
+#pragma unroll
+    for (int d = 0; d < NS; ++d) {
+      Pv[0][d] = XV[d];
+      Pv[1][d] = XV[d];
+    }
+    Pv[0][NS] = tb;
+    Pv[1][NS] = tt;
+    int c = 2;
+#pragma unroll
+    for (int k = 0; k <= NS; ++k) {
+      const int w = vs[k];
+      if (k == k1 || w == V) continue;
+#pragma unroll
+      for (int i = 2; i <= NS; ++i)
+        if (i == c) {
+          for (int d = 0; d < NS; ++d) Pv[i][d] = P.coords[(size_t)w * NS + d];
+          Pv[i][NS] = P.tau[w];
+        }
+      ++c;
+    }
+    double E[NS][NS + 1], Gm[NS][NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+      for (int d = 0; d <= NS; ++d) E[i][d] = Pv[i + 1][d] - Pv[0][d];
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int d = 0; d <= NS; ++d) sacc += E[i][d] * E[j][d];
+        Gm[i][j] = sacc;
+      }
+    double detG;
+    if (NS == 1)
+      detG = Gm[0][0];
+    else if (NS == 2)
+      detG = Gm[0][0] * Gm[1][1] - Gm[0][1] * Gm[1][0];
+    else
+      detG = Gm[0][0] * (Gm[1][1] * Gm[2][2] - Gm[1][2] * Gm[2][1]) -
+             Gm[0][1] * (Gm[1][0] * Gm[2][2] - Gm[1][2] * Gm[2][0]) +
+             Gm[0][2] * (Gm[1][0] * Gm[2][1] - Gm[1][1] * Gm[2][0]);
+    G0[0] = sqrt(fmax(detG, 0.0));
+    int g1 = 0;
+    for (int i = 0; i < npatch; ++i)
+      if ((int)EL[i * ELS + El<NS>::E] == e1) g1 = (int)EL[i * ELS + El<NS>::GRP];
+    G0[1] = (double)g1;
+    const double* gl = P.grad_lam + ((size_t)e1 * (NS + 1) + k1) * NS;
+    double nn = 0.0;
+#pragma unroll
+    for (int d = 0; d < NS; ++d) nn += gl[d] * gl[d];
+    nn = sqrt(nn);
+#pragma unroll
+    for (int d = 0; d < NS; ++d) G0[2 + d] = -gl[d] / nn;
+#pragma unroll
+    for (int i = 0; i <= NS; ++i)
+#pragma unroll
+      for (int d = 0; d <= NS; ++d) G0[2 + NS + i * (NS + 1) + d] = Pv[i][d];
+  }
+  __syncthreads();
+  if (nbf > 0) {
+    if (tid == 0) {
+      int c = 0;
+      for (int r = 0; r < m; ++r) {
+        s_foff[r] = c;
+        for (int f = 0; f < nbf; ++f)
+          if ((int)FG[f * FGS + 1] == r) s_fl[c++] = f;
+      }
+      s_foff[m] = c;
+    }
+    __syncthreads();
+    const long long gbase = P.bpt_off[tent];
+    double* PN = PG;  // per-point outward normal (PCH x NS)
+    for (int r = 0; r < m; ++r) {
+      const int nf = s_foff[r + 1] - s_foff[r];
+      if (nf == 0) continue;
+      const double cr = gc[r], hr = gh[r];
+      const int npts = nf * Q;
+      for (int f0 = 0; f0 < npts; f0 += PCH) {
+        const int nc = min(PCH, npts - f0);
+        for (int pt = tid; pt < PCH; pt += blockDim.x) {
+          double y[NS + 1];
+#pragma unroll
+          for (int d = 0; d < NS; ++d) y[d] = XV[d];
+          y[NS] = tmid;
+          double w = 0.0, g = 0.0;
+          if (pt < nc) {
+            const int fi = s_fl[s_foff[r] + (f0 + pt) / Q];
+            const int q = (f0 + pt) % Q;
+            const double* G0 = FG + fi * FGS;
+            const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+#pragma unroll
+            for (int d = 0; d <= NS; ++d) y[d] = 0.0;
+#pragma unroll
+            for (int k = 0; k <= NS; ++k)
+#pragma unroll
+              for (int d = 0; d <= NS; ++d) y[d] += lam[k] * G0[2 + NS + k * (NS + 1) + d];
+            w = P.w_ref[q] * G0[0];
+            g = P.gD[gbase + (long long)fi * Q + q];
+#pragma unroll
+            for (int d = 0; d < NS; ++d) PN[pt * NS + d] = G0[2 + d];
+          }
+          PV[pt * (NS + 1)] = cr * (y[NS] - tmid) / hr;
+#pragma unroll
+          for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (y[d] - XV[d]) / hr;
+          PW[pt] = w;
+          PD[pt] = g;
+        }
+        __syncthreads();
+        monomials<NS>(T, T.M1, p, PV, POW, MT, PCH, PCH);
+        __syncthreads();
+        for (int i = tid; i < PCH * NW; i += blockDim.x) {
+          const int pt = i % PCH, j = i / PCH;
+          const double w = PW[pt], sw = sqrt(w), g = PD[pt];
+          double fl[NS + 1], uu;
+          eval_j<NS, false>(T, j, MT, PCH, pt, fl, &uu);
+          const double v = cr * fl[0];
+          double sn = 0.0;
+          if (pt < nc)
+#pragma unroll
+            for (int d = 0; d < NS; ++d) sn += fl[1 + d] * PN[pt * NS + d];
+          F1[pt * NWP + j] = sw * v;
+          F1[(PCH + pt) * NWP + j] = sw * (P.alpha * v + sn);
+          F1[(2 * PCH + pt) * NWP + j] = w * g * (P.alpha * v - sn);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < NW * NW; idx += blockDim.x) {
+          const int ii = idx / NW, jj = idx % NW;
+          double acc = 0.0;
+          for (int k = 0; k < nc; ++k) acc += F1[k * NWP + ii] * F1[(PCH + k) * NWP + jj];
+          A[(long long)(r * NW + ii) * lda + r * NW + jj] += acc;
+        }
+        for (int j = tid; j < NW; j += blockDim.x) {
+          double acc = 0.0;
+          for (int k = 0; k < nc; ++k) acc += F1[(2 * PCH + k) * NWP + j];
+          A[(long long)(r * NW + j) * lda + S] += acc;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // 3b. speed interfaces, one face at a time
+  for (int f = nbf; f < nbf + nif; ++f) {
+    const bool dir = false;
     int e1, k1, e2 = -1;
     if (dir) {
       e1 = P.vb[2 * (P.vb_ptr[V] + f)];
@@ -702,8 +866,8 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
         for (int i = tid; i < PCH * NW; i += blockDim.x) {
           const int pt = i % PCH, j = i / PCH;
           const double w = PW[pt], sw = sqrt(w), g = PD[pt];
-          double fl[NS + 1];
-          fields<NS>(T, j, MT, PCH, pt, fl);
+          double fl[NS + 1], uu;
+          eval_j<NS, false>(T, j, MT, PCH, pt, fl, &uu);
           const double v = cr * fl[0];
           double sn = 0.0;
           for (int d = 0; d < NS; ++d) sn += fl[1 + d] * nrm[d];
@@ -759,9 +923,9 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
 
   // ---- 4. LU with partial pivoting, back substitution, U constants ----------------
   bool ok;
-  if (S <= 64 && L.A_in_lds) {
+  if (S <= 32 && L.A_in_lds) {
     bool w_ok = true;
-    if (wave == 0) w_ok = wave_lu_solve(A, (int)lda, S, xs);
+    if (wave == 0) w_ok = wave_lu_regs<32>(A, (int)lda, S, xs);
     if (wave == 0 && lane == 0 && !w_ok) s_err = kStatSingular;
     __syncthreads();
     ok = s_err == 0;
@@ -781,24 +945,13 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
   __syncthreads();
 
   // ---- 5. top values overwrite the stored values -----------------------------------
-  double* cm = W1;                    // (NS+1) x M1: field coefficients contracted with x
-  double* cu = W1 + (NS + 1) * T.M1;  // M: U coefficients contracted with x
+  double* cm = W1;  // (NS+2) x M: coefficients of v, sigma, U on the monomials, contracted with x
   for (int r = 0; r < m; ++r) {
     const double cr = gc[r], hr = gh[r];
-    for (int i = tid; i < (NS + 1) * T.M1 + T.M; i += blockDim.x) cm[i] = 0.0;
-    __syncthreads();
-    if (tid <= NS) {
-      const int comp = tid;
-      for (int j = 0; j < NW; ++j) {
-        const double xj = xs[r * NW + j];
-        const int row = j * (NS + 1) + comp;
-        for (int e = T.fo_ptr[row]; e < T.fo_ptr[row + 1]; ++e) cm[comp * T.M1 + T.fo_idx[e]] += T.fo_coef[e] * xj;
-      }
-    } else if (tid == NS + 1) {
-      for (int j = 0; j < NW; ++j) {
-        const double xj = xs[r * NW + j] * hr;
-        for (int e = T.u_ptr[j]; e < T.u_ptr[j + 1]; ++e) cu[T.u_idx[e]] += T.u_coef[e] * xj;
-      }
+    for (int row = tid; row < (NS + 2) * T.M; row += blockDim.x) {
+      double acc = 0.0;
+      for (int e = T.tr_ptr[row]; e < T.tr_ptr[row + 1]; ++e) acc += T.tr_coef[e] * xs[r * NW + T.tr_j[e]];
+      cm[row] = row >= (NS + 1) * T.M ? acc * hr : acc;
     }
     __syncthreads();
     const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
@@ -832,11 +985,11 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
         const int pt = i % nc, comp = i / nc;
         double acc = 0.0;
         if (comp <= NS) {
-          for (int k = 0; k < T.M1; ++k) acc += cm[comp * T.M1 + k] * MT[k * LD2 + pt];
+          for (int k = 0; k < T.M1; ++k) acc += cm[comp * T.M + k] * MT[k * LD2 + pt];
           if (comp == 0) acc *= cr;
         } else {
           acc = a0[r];
-          for (int k = 0; k < T.M; ++k) acc += cu[k] * MT[k * LD2 + pt];
+          for (int k = 0; k < T.M; ++k) acc += cm[(NS + 1) * T.M + k] * MT[k * LD2 + pt];
         }
         const int f = f0 + pt;
         const int li = s_gel[s_goff[r] + f / Q];

@@ -200,6 +200,58 @@ Table build_table(int n, int p) {
       }
     T.u_ptr[j + 1] = (int)T.u_idx.size();
   }
+  // entry form: one entry per term a x^alpha t^k of U_j, with the derivative terms
+  // k a x^alpha t^(k-1) (v) and -alpha_m a x^(alpha-e_m) t^k (sigma_m)
+  const int ns = n + 2;
+  T.ue_ptr.assign((size_t)T.NW + 1, 0);
+  for (int j = 0; j < T.NW; ++j) {
+    for (auto& kv : basis[j + 1]) {
+      const Key key = kv.first;
+      const Rat a = kv.second;
+      T.ue_idx.push_back(index.at(key));
+      T.ue_coef.push_back(a.to_double());
+      if (key[0] > 0) {
+        Key d = key;
+        d[0]--;
+        T.ue_idx.push_back(index.at(d));
+        T.ue_coef.push_back(a.mul(key[0]).to_double());
+      } else {
+        T.ue_idx.push_back(0);
+        T.ue_coef.push_back(0.0);
+      }
+      for (int m = 1; m <= n; ++m) {
+        if (key[m] > 0) {
+          Key d = key;
+          d[m]--;
+          T.ue_idx.push_back(index.at(d));
+          T.ue_coef.push_back(a.mul(-key[m]).to_double());
+        } else {
+          T.ue_idx.push_back(0);
+          T.ue_coef.push_back(0.0);
+        }
+      }
+    }
+    T.ue_ptr[j + 1] = (int)(T.ue_idx.size() / ns);
+  }
+  // transposed form: rows comp*M + monomial
+  {
+    std::vector<std::vector<std::pair<int, double>>> rows((size_t)ns * T.M);
+    for (int j = 0; j < T.NW; ++j)
+      for (int comp = 0; comp <= n; ++comp)
+        for (int e = T.fo_ptr[(size_t)j * (n + 1) + comp]; e < T.fo_ptr[(size_t)j * (n + 1) + comp + 1]; ++e)
+          rows[(size_t)comp * T.M + T.fo_idx[e]].push_back({j, T.fo_coef[e]});
+    for (int j = 0; j < T.NW; ++j)
+      for (int e = T.u_ptr[j]; e < T.u_ptr[j + 1]; ++e)
+        rows[(size_t)(n + 1) * T.M + T.u_idx[e]].push_back({j, T.u_coef[e]});
+    T.tr_ptr.assign(rows.size() + 1, 0);
+    for (size_t r = 0; r < rows.size(); ++r) {
+      for (auto& pr : rows[r]) {
+        T.tr_j.push_back(pr.first);
+        T.tr_coef.push_back(pr.second);
+      }
+      T.tr_ptr[r + 1] = (int)T.tr_j.size();
+    }
+  }
   return T;
 }
 

@@ -150,8 +150,8 @@ class Tents:
         return list(zip(self.vertex.tolist(), self.t_bot.tolist(), self.t_top.tolist()))
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().tent_free(self._h)
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.tent_free(self._h)
             self._h = None
 
 
@@ -268,6 +268,6 @@ class Trefftz:
         return dict(N=N.value, nnz_fields=nnz.value, n_mono=M.value, Q=Q.value)
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().trefftz_destroy(self._h)
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.trefftz_destroy(self._h)
             self._h = None
