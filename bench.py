@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (automatic shape)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
@@ -121,6 +122,12 @@ def main():
     if ctx.nb:
         bx = ctx.boundary_points()
         ctx.set_boundary(f.v(bx[:, :-1], bx[:, -1]))
+    tuned = None
+    if not args.no_tune:
+        from paper_1907_02367_amd.autotune import autotune
+
+        tuned, _ = autotune(ctx, use_cache=False)
+    shape = ctx.get_tuning()
     flops, bytes_, N = op_counts(ctx, pr, tents)
     L = tents.n_layers
     lp = tents.layer_ptr
@@ -155,6 +162,19 @@ def main():
     flops_per_launch = layer_flops.mean()
     achieved = flops_per_launch / avg_launch_s
     e_abs, e_rel = ctx.eval_error(f.v(xq, pr.T), f.sigma(xq, pr.T))
+    # the same sweep recorded once as a HIP graph and replayed (informational)
+    gstream = torch.cuda.Stream()
+    with torch.cuda.stream(gstream):
+        ctx.capture_sweep(0, L, with_reset=True, stream=gstream.cuda_stream)
+        for _ in range(args.warmup):
+            ctx.replay_sweep(gstream.cuda_stream)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.replay_sweep(gstream.cuda_stream)
+        torch.cuda.synchronize()
+        graph_ms = 1e3 * (time.perf_counter() - g0) / args.steps
+    ctx.status()
     dofs = float(tents.n_tents * N)
     out = {
         "metric": METRIC,
@@ -174,6 +194,8 @@ def main():
             "tents": int(tents.n_tents), "layers": int(L), "dofs_per_tent": int(N),
             "dof_updates_per_step": dofs, "e_abs_at_T": e_abs, "e_rel_at_T": e_rel,
             "kernel_ms_per_step": float(kern_ms.sum(axis=1).mean()),
+            "graph_replay_ms_per_step": graph_ms,
+            "kernel_shape": shape, "autotuned": tuned is not None,
             "parallelism": "single GPU, all tents of a layer in one launch",
         },
         "roofline": {

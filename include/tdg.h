@@ -146,8 +146,9 @@ int trefftz_layer_solve(tdg_ctx* ctx, int32_t layer_begin, int32_t layer_end, co
 int trefftz_eval_error(tdg_ctx* ctx, const double* v_ex, const double* sigma_ex, double* e_abs, double* e_rel,
                        tdg_stream stream);
 /* Energy on the current front, E = 1/2 int c^-2 v^2 + |sigma|^2 - 2 v sigma.grad phi
- * (the energy of Sec. 6.5 where the front is flat), and the summed per-tent
- * dissipation of the tents solved since the last reset.  Synchronises. */
+ * (the energy of Sec. 6.5 where the front is flat), and the sum over tents of
+ * the per-tent indicator eta_T (see trefftz_set_indicator; 0 for tents solved
+ * with the indicator off since the last bind).  Synchronises. */
 int trefftz_energy(tdg_ctx* ctx, double* E_front, double* dissipated, tdg_stream stream);
 /* Synchronises the stream and returns the first error a kernel reported. */
 int trefftz_status(tdg_ctx* ctx, tdg_stream stream);
@@ -159,6 +160,87 @@ int trefftz_read_state(tdg_ctx* ctx, double* v, double* sigma, double* U, tdg_st
  * n_mono = monomials t^k x^alpha with k + |alpha| <= p, and the points per
  * element Q.  For operation counts; any output pointer may be NULL. */
 int trefftz_table_info(const tdg_ctx* ctx, int32_t p, int32_t* N, int32_t* nnz_fields, int32_t* n_mono, int32_t* Q);
+/* Execution shape of the tent kernel (all tents of a layer in one launch):
+ * pts_per_chunk = quadrature points staged per chunk (0 = largest that fits in
+ * LDS, else 4, 8, 16, 32 or 64 if it fits); persistent = 1: a grid of resident
+ * workgroups takes the layer's tents from a device counter (balances tents of
+ * uneven size and degree), 0: one workgroup per tent.  Results do not depend
+ * on the shape.  TDG_EINVAL if the shape does not fit. */
+int trefftz_set_tuning(tdg_ctx* ctx, int32_t pts_per_chunk, int32_t persistent);
+int trefftz_get_tuning(const tdg_ctx* ctx, int32_t* pts_per_chunk, int32_t* persistent, int32_t* lds_bytes);
+/* Records layers [layer_begin, layer_end) (as trefftz_layer_solve, preceded by
+ * trefftz_reset if with_reset) into a HIP graph owned by the context, captured
+ * on `stream` (which must not be the default stream).  trefftz_replay_sweep
+ * launches the recorded graph on a stream: same buffers, same degrees.  A new
+ * capture replaces the previous graph. */
+int trefftz_capture_sweep(tdg_ctx* ctx, int32_t layer_begin, int32_t layer_end, const int8_t* p_per_tent,
+                          int32_t with_reset, tdg_stream stream);
+int trefftz_replay_sweep(tdg_ctx* ctx, tdg_stream stream);
+/* Per-tent outputs of the last solve of tents [first_tent, first_tent+count):
+ * ir_steps = refinement steps of the mixed-precision solve (+1000 where the
+ * tent fell back to the FP64 Gram; 0 in FP64 contexts), dissipation = the
+ * indicator eta_T of trefftz_set_indicator (0 where it was not computed).
+ * Either pointer may be NULL.  Synchronises. */
+int trefftz_tent_stats(tdg_ctx* ctx, int64_t first_tent, int64_t count, int32_t* ir_steps, double* dissipation,
+                       tdg_stream stream);
+
+/* ---- per-tent degree (learned degree selection) -------------------------------
+ * Indicator of a tent (a term of its energy balance, from eq. 4.1 with w = u):
+ *   eta_T = 1/2 int_{bottom} c^-2 dv^2 + |dsigma|^2 - 2 dv dsigma.grad phi_old,
+ * (dv, dsigma) = tent solution minus the incoming values at the bottom points,
+ * i.e. the energy of the jump the tent's Trefftz space cannot match; it
+ * shrinks with the degree where the solution is smooth.  All arrays below are
+ * device arrays indexed by the global tent number (n_tents entries; a call
+ * writes the entries of its layers only). */
+
+/* on = 1: trefftz_layer_solve also computes eta_T (into the per-tent outputs
+ * of trefftz_tent_stats); 0 (the default) skips it. */
+int trefftz_set_indicator(tdg_ctx* ctx, int32_t on);
+/* Features of the tents of `layer` from the current front and stored values
+ * (call after the layers below it are solved): feats[tent*8 + k],
+ *   0 log(dt c_max / h_V)  1 log h_V  2 |patch| / 16  3 log c_max
+ *   4 log(c_max / c_min)  5 log(incoming energy / patch volume)
+ *   6 log(relative spread of the incoming values inside the patch elements)
+ *   7 1 if V lies on the Dirichlet boundary,
+ * with h_V the largest distance from X_V to a patch vertex and dt the tent
+ * height. */
+int trefftz_tent_features(tdg_ctx* ctx, int32_t layer, float* feats, tdg_stream stream);
+/* eta_T of every tent of `layer` solved at degree p (1..p_max), written to
+ * eta[tent]; stored values and front are left untouched (a probe). */
+int trefftz_layer_indicator(tdg_ctx* ctx, int32_t layer, int32_t p, double* eta, tdg_stream stream);
+/* Solves layers [layer_begin, layer_end) with a degree per tent.  With a
+ * network (w_bf16, tdg_mlp_nparam() BF16 values): per layer, features ->
+ * feats, the network's predicted log eta_T(p) for p = 2..8 -> p_sel[tent] =
+ * the smallest p <= p_max whose prediction is <= log_eta_tol (else p_max); a
+ * tent whose realised eta_T exceeds eta_tol (if > 0) is solved again at p_max
+ * before anything is written.  w_bf16 = NULL: fixed p_max everywhere (the
+ * fallback; p_sel is filled with p_max).  p_used (nullable) gets the degree
+ * each tent was finally solved with, eta (nullable) its eta_T. */
+int trefftz_layer_solve_adaptive(tdg_ctx* ctx, int32_t layer_begin, int32_t layer_end, const uint16_t* w_bf16,
+                                 float log_eta_tol, double eta_tol, float* feats, int8_t* p_sel, int8_t* p_used,
+                                 double* eta, tdg_stream stream);
+
+/* ---- degree network: 3 dense layers 8 -> 64 -> 64 -> 7, tanh, BF16 weights,
+ * FP32 arithmetic.  Parameter vector (tdg_mlp_nparam() values): W1[64][8],
+ * b1[64], W2[64][64], b2[64], W3[7][64], b3[7] (row-major, out x in).  Every
+ * pointer is a device pointer; the calls only enqueue work on the stream. */
+int tdg_mlp_nparam(void);
+/* y[n][7] = network(x[n][8]) with the BF16 weights w_bf16. */
+int tdg_mlp_forward(const uint16_t* w_bf16, const float* x, int64_t n, float* y, tdg_stream stream);
+/* Gradient of L = sum_s sum_o mask[s][o] (y[s][o] - target[s][o])^2 / norm
+ * with respect to the parameters (at the BF16 weights) into grad[0..nparam-1]
+ * and L into grad[nparam] (nparam+1 floats); n >= 1, norm > 0.  partial:
+ * scratch of ceil(n/32) * (nparam+1) floats.  Blocks of 32 samples are summed
+ * in block order (deterministic). */
+int tdg_mlp_backward(const uint16_t* w_bf16, const float* x, const float* target, const float* mask, int64_t n,
+                     float norm, float* partial, float* grad, tdg_stream stream);
+/* One Adam step (Kingma and Ba) on the FP32 master weights w32 with moments
+ * m, v (step >= 1 counts from 1), then w_bf16 = round-to-nearest-even(w32). */
+int tdg_mlp_adam(float* w32, uint16_t* w_bf16, const float* grad, float* m, float* v, int32_t step, float lr,
+                 float b1, float b2, float eps, tdg_stream stream);
+/* w_bf16 = round-to-nearest-even(w32). */
+int tdg_mlp_round(const float* w32, uint16_t* w_bf16, tdg_stream stream);
+
 void trefftz_destroy(tdg_ctx* ctx);
 const char* tdg_last_error(void);
 

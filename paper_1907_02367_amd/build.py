@@ -27,6 +27,7 @@ SOURCES = [
     ("api.cpp", []),
     ("tent_kernel.hip", []),
     ("reduce.hip", []),
+    ("mlp.hip", []),
 ]
 
 ARCH = os.environ.get("TDG_OFFLOAD_ARCH", "gfx950")

@@ -69,7 +69,10 @@ struct tdg_ctx {
   bool bound = false;
   KParams kp{};
   LdsPlan lp{};
-  size_t w_ex = 0, w_partial = 0, w_out = 0, w_status = 0, w_sys = 0;  // offsets in doubles inside WORK
+  size_t w_ex = 0, w_partial = 0, w_out = 0, w_status = 0, w_sys = 0, w_ctr = 0;  // offsets in doubles inside WORK
+  int persistent = 0, ncu = 256, resident = 1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   int64_t sys_stride = 0;  // doubles per workgroup for systems kept in global memory
   int nblocks_red = 256;
 };
@@ -97,7 +100,7 @@ int fail(int code, const std::string& msg) {
 // element-record size of the tent kernel (see El<NS> in the kernel)
 int el_size(int n) { return (n + 1) * n + (n + 1) + 2 * n + 5; }
 
-int plan_lds(tdg_ctx* X) {
+int plan_lds(tdg_ctx* X, int forced_pch = 0) {
   const int n = X->topo.n;
   const Table& Tm = X->tabs[X->opts.p_max];
   LdsPlan& L = X->lp;
@@ -111,7 +114,7 @@ int plan_lds(tdg_ctx* X) {
   int tpw = (ntiles + kBlock / 64 - 1) / (kBlock / 64);
   L.TPW = 1;
   while (L.TPW < tpw) L.TPW *= 2;
-  if (L.TPW > 16) return fail(TDG_EINVAL, "degree too high for the tent kernel (more than 16 Gram tiles per wave)");
+  if (L.TPW > 16) L.TPW = 16;  // more tiles: several passes over the points
   L.M = Tm.M;
   L.maxpatch = maxpatch;
   L.ELS = el_size(n);
@@ -129,7 +132,7 @@ int plan_lds(tdg_ctx* X) {
   const Choice order[4] = {{true, true, 16}, {true, false, 16}, {false, true, 4}, {false, false, 4}};
   for (const Choice& ch : order) {
     for (int pch : {64, 32, 16, 8, 4}) {
-      if (pch < ch.min_pch) continue;
+      if (forced_pch ? pch != forced_pch : pch < ch.min_pch) continue;
       L.PCH = pch;
       L.A_in_lds = ch.a;
       L.tab_in_lds = ch.t;
@@ -149,6 +152,9 @@ int plan_lds(tdg_ctx* X) {
       L.off_fg = take((long long)std::max(L.maxfaces, 1) * (2 + n + (n + 1) * (n + 1)));
       L.off_tab = ch.t ? take(tab_dbl) : 0;
       L.off_A = ch.a ? take((long long)L.S * L.lda) : 0;
+      const bool mixed = X->opts.precision == 1;
+      L.off_AF = (mixed && ch.a) ? take((long long)L.S * L.lda) : 0;
+      L.off_vec = mixed ? take(2LL * L.S) : 0;
       L.total = off;
       if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) return TDG_OK;
     }
@@ -335,12 +341,13 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   X->w_partial = (size_t)(X->nq * (n + 1) + 31) / 32 * 32;
   X->w_out = X->w_partial + 2 * X->nblocks_red + 32;
   X->w_status = X->w_out + 32;
-  X->w_sys = X->w_status + 32;
+  X->w_ctr = X->w_status + 32;
+  X->w_sys = X->w_ctr + ((X->tents.layer_ptr.size() + 1) / 2 + 31) / 32 * 32;
   {
     int64_t widest = 0;
     for (size_t l = 0; l + 1 < X->tents.layer_ptr.size(); ++l)
       widest = std::max<int64_t>(widest, X->tents.layer_ptr[l + 1] - X->tents.layer_ptr[l]);
-    X->sys_stride = X->lp.A_in_lds ? 0 : ((int64_t)X->lp.S * X->lp.lda + 31) / 32 * 32;
+    X->sys_stride = X->lp.A_in_lds ? 0 : ((int64_t)X->lp.S * X->lp.lda * (X->opts.precision == 1 ? 2 : 1) + 31) / 32 * 32;
     X->sizes[TDG_BUF_WORK] = (int64_t)(X->w_sys + X->sys_stride * widest) * 8;
   }
   X->sizes[TDG_BUF_TENT] = std::max<int64_t>((int64_t)X->tents.V.size(), 1) * 16;
@@ -435,6 +442,11 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
   P.ir_steps = (int*)((double*)X->dev[TDG_BUF_TENT] + X->tents.V.size());
   P.work = W + X->w_sys;
   P.work_stride = X->sys_stride;
+  P.p_fixed = 0;
+  P.indicator = 0;
+  P.write_back = 1;
+  P.eta_tol = 0.0;
+  P.p_used = nullptr;
   for (int p = 0; p <= kMaxP; ++p) P.tab[p] = TableDesc{};
   for (int p = 1; p <= X->opts.p_max; ++p) {
     const Table& tb = X->tabs[p];
@@ -466,6 +478,12 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
     D.u_coef = F + o.u_coef;
   }
   if (set_kernel_smem_limit(T.n, (size_t)X->lp.total * 8 + 64)) return fail(TDG_EHIP, "cannot raise the LDS limit");
+  {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&X->ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    X->resident = resident_blocks_per_cu(T.n, X->lp.TPW, X->opts.precision == 1, (size_t)X->lp.total * 8);
+  }
   // clear state, front, status, per-tent outputs
   if (launch_fill(P.state, 0.0, X->nq * (T.n + 2), stream) || launch_fill(P.tau, 0.0, T.nv, stream) ||
       launch_fill(W + X->w_status, 0.0, 32, stream) ||
@@ -529,13 +547,100 @@ int trefftz_layer_solve(tdg_ctx* X, int32_t layer_begin, int32_t layer_end, cons
   if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
   const int nl = (int)X->tents.layer_ptr.size() - 1;
   if (layer_begin < 0 || layer_end > nl || layer_begin > layer_end) return fail(TDG_EINVAL, "layer range out of bounds");
-  if (X->opts.precision != 0) return fail(TDG_EINVAL, "this build solves in FP64 only (precision = 0)");
   KParams P = X->kp;
   P.p_per_tent = (const signed char*)p_per_tent;
+  int* ctr = (int*)((double*)X->dev[TDG_BUF_WORK] + X->w_ctr);
+  if (X->persistent && layer_end > layer_begin &&
+      launch_fill((double*)X->dev[TDG_BUF_WORK] + X->w_ctr, 0.0, ((long long)nl + 1 + 1) / 2, stream))
+    return fail(TDG_EHIP, "fill kernel launch failed");
+  const int grid_max = std::max(1, X->ncu * X->resident);
   for (int l = layer_begin; l < layer_end; ++l) {
     const int t0 = (int)X->tents.layer_ptr[l];
     const int cnt = (int)(X->tents.layer_ptr[l + 1] - X->tents.layer_ptr[l]);
-    if (launch_layer(P, X->lp, t0, cnt, stream)) return fail(TDG_EHIP, "tent kernel launch failed");
+    const int g = std::min(cnt, grid_max);
+    if (launch_layer(P, X->lp, t0, cnt, g, X->persistent ? ctr + l : nullptr, stream))
+      return fail(TDG_EHIP, "tent kernel launch failed");
+  }
+  return TDG_OK;
+}
+
+int trefftz_set_indicator(tdg_ctx* X, int32_t on) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  X->kp.indicator = on ? 1 : 0;
+  return TDG_OK;
+}
+
+int trefftz_tent_features(tdg_ctx* X, int32_t layer, float* feats, tdg_stream stream) {
+  if (!X || !feats) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  const int nl = (int)X->tents.layer_ptr.size() - 1;
+  if (layer < 0 || layer >= nl) return fail(TDG_EINVAL, "layer out of bounds");
+  const int t0 = (int)X->tents.layer_ptr[layer];
+  const int cnt = (int)(X->tents.layer_ptr[layer + 1] - t0);
+  if (launch_features(X->kp, t0, cnt, feats, stream)) return fail(TDG_EHIP, "feature kernel launch failed");
+  return TDG_OK;
+}
+
+int trefftz_layer_indicator(tdg_ctx* X, int32_t layer, int32_t p, double* eta, tdg_stream stream) {
+  if (!X || !eta) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  const int nl = (int)X->tents.layer_ptr.size() - 1;
+  if (layer < 0 || layer >= nl) return fail(TDG_EINVAL, "layer out of bounds");
+  if (p < 1 || p > X->opts.p_max) return fail(TDG_EINVAL, "degree outside [1, p_max]");
+  KParams P = X->kp;
+  P.p_per_tent = nullptr;
+  P.p_fixed = p;
+  P.indicator = 1;
+  P.write_back = 0;
+  P.eta_tol = 0.0;
+  P.dissip = eta;
+  P.p_used = nullptr;
+  const int t0 = (int)X->tents.layer_ptr[layer];
+  const int cnt = (int)(X->tents.layer_ptr[layer + 1] - t0);
+  const int g = std::min(cnt, std::max(1, X->ncu * X->resident));
+  int* ctr = (int*)((double*)X->dev[TDG_BUF_WORK] + X->w_ctr);
+  if (X->persistent && cnt > 0 && launch_fill((double*)X->dev[TDG_BUF_WORK] + X->w_ctr + layer / 2, 0.0, 1, stream))
+    return fail(TDG_EHIP, "fill kernel launch failed");
+  if (launch_layer(P, X->lp, t0, cnt, g, X->persistent ? ctr + layer : nullptr, stream))
+    return fail(TDG_EHIP, "tent kernel launch failed");
+  return TDG_OK;
+}
+
+int trefftz_layer_solve_adaptive(tdg_ctx* X, int32_t layer_begin, int32_t layer_end, const uint16_t* w_bf16,
+                                 float log_eta_tol, double eta_tol, float* feats, int8_t* p_sel, int8_t* p_used,
+                                 double* eta, tdg_stream stream) {
+  if (!X || !feats || !p_sel) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  const int nl = (int)X->tents.layer_ptr.size() - 1;
+  if (layer_begin < 0 || layer_end > nl || layer_begin > layer_end) return fail(TDG_EINVAL, "layer range out of bounds");
+  if (!(eta_tol >= 0.0)) return fail(TDG_EINVAL, "eta_tol must be >= 0");
+  KParams P = X->kp;
+  P.p_per_tent = (const signed char*)p_sel;
+  P.eta_tol = w_bf16 ? eta_tol : 0.0;
+  P.p_used = (signed char*)p_used;
+  if (eta) {
+    P.dissip = eta;
+    P.indicator = 1;
+  }
+  int* ctr = (int*)((double*)X->dev[TDG_BUF_WORK] + X->w_ctr);
+  if (X->persistent && layer_end > layer_begin &&
+      launch_fill((double*)X->dev[TDG_BUF_WORK] + X->w_ctr, 0.0, ((long long)nl + 1 + 1) / 2, stream))
+    return fail(TDG_EHIP, "fill kernel launch failed");
+  const int grid_max = std::max(1, X->ncu * X->resident);
+  for (int l = layer_begin; l < layer_end; ++l) {
+    const int t0 = (int)X->tents.layer_ptr[l];
+    const int cnt = (int)(X->tents.layer_ptr[l + 1] - X->tents.layer_ptr[l]);
+    if (w_bf16) {
+      if (launch_features(P, t0, cnt, feats, stream) ||
+          launch_select((const unsigned short*)w_bf16, feats, t0, cnt, log_eta_tol, X->opts.p_max,
+                        (signed char*)p_sel, stream))
+        return fail(TDG_EHIP, "degree selection launch failed");
+    } else if (launch_fill_i8((signed char*)p_sel + t0, (signed char)X->opts.p_max, cnt, stream)) {
+      return fail(TDG_EHIP, "fill kernel launch failed");
+    }
+    if (launch_layer(P, X->lp, t0, cnt, std::min(cnt, grid_max), X->persistent ? ctr + l : nullptr, stream))
+      return fail(TDG_EHIP, "tent kernel launch failed");
   }
   return TDG_OK;
 }
@@ -634,6 +739,93 @@ int trefftz_table_info(const tdg_ctx* X, int32_t p, int32_t* N, int32_t* nnz_fie
   return TDG_OK;
 }
 
-void trefftz_destroy(tdg_ctx* X) { delete X; }
+int trefftz_set_tuning(tdg_ctx* X, int32_t pts_per_chunk, int32_t persistent) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (persistent != 0 && persistent != 1) return fail(TDG_EINVAL, "persistent must be 0 or 1");
+  if (pts_per_chunk != 0 && pts_per_chunk != 4 && pts_per_chunk != 8 && pts_per_chunk != 16 && pts_per_chunk != 32 &&
+      pts_per_chunk != 64)
+    return fail(TDG_EINVAL, "pts_per_chunk must be 0, 4, 8, 16, 32 or 64");
+  const LdsPlan old = X->lp;
+  int rc = plan_lds(X, pts_per_chunk);
+  if (rc == TDG_OK && X->lp.A_in_lds != old.A_in_lds) rc = fail(TDG_EINVAL, "shape changes where the systems live");
+  if (rc != TDG_OK) {
+    X->lp = old;
+    return rc;
+  }
+  X->persistent = persistent;
+  if (X->bound) {
+    if (set_kernel_smem_limit(X->topo.n, (size_t)X->lp.total * 8 + 64)) return fail(TDG_EHIP, "cannot raise the LDS limit");
+    X->resident = resident_blocks_per_cu(X->topo.n, X->lp.TPW, X->opts.precision == 1, (size_t)X->lp.total * 8);
+  }
+  return TDG_OK;
+}
+
+int trefftz_get_tuning(const tdg_ctx* X, int32_t* pts_per_chunk, int32_t* persistent, int32_t* lds_bytes) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (pts_per_chunk) *pts_per_chunk = X->lp.PCH;
+  if (persistent) *persistent = X->persistent;
+  if (lds_bytes) *lds_bytes = X->lp.total * 8;
+  return TDG_OK;
+}
+
+static void drop_graph(tdg_ctx* X) {
+  if (X->graph_exec) hipGraphExecDestroy(X->graph_exec);
+  if (X->graph) hipGraphDestroy(X->graph);
+  X->graph_exec = nullptr;
+  X->graph = nullptr;
+}
+
+int trefftz_capture_sweep(tdg_ctx* X, int32_t layer_begin, int32_t layer_end, const int8_t* p_per_tent,
+                          int32_t with_reset, tdg_stream stream) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  if (!stream) return fail(TDG_EINVAL, "capture needs a non-default stream");
+  drop_graph(X);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = with_reset ? trefftz_reset(X, stream) : TDG_OK;
+  if (rc == TDG_OK) rc = trefftz_layer_solve(X, layer_begin, layer_end, p_per_tent, stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc != TDG_OK) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(TDG_EHIP, std::string("stream capture failed: ") + hipGetErrorString(e));
+  X->graph = g;
+  e = hipGraphInstantiate(&X->graph_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(X);
+    return fail(TDG_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+  }
+  return TDG_OK;
+}
+
+int trefftz_replay_sweep(tdg_ctx* X, tdg_stream stream) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->graph_exec) return fail(TDG_ESTATE, "trefftz_capture_sweep first");
+  HIP_OK(hipGraphLaunch(X->graph_exec, (hipStream_t)stream));
+  return TDG_OK;
+}
+
+int trefftz_tent_stats(tdg_ctx* X, int64_t first_tent, int64_t count, int32_t* ir_steps, double* dissipation,
+                       tdg_stream stream) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  const int64_t nt = (int64_t)X->tents.V.size();
+  if (first_tent < 0 || count < 0 || first_tent + count > nt) return fail(TDG_EINVAL, "tent range out of bounds");
+  hipStream_t s = (hipStream_t)stream;
+  if (ir_steps && count)
+    HIP_OK(hipMemcpyAsync(ir_steps, X->kp.ir_steps + first_tent, count * 4, hipMemcpyDeviceToHost, s));
+  if (dissipation && count)
+    HIP_OK(hipMemcpyAsync(dissipation, X->kp.dissip + first_tent, count * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return TDG_OK;
+}
+
+void trefftz_destroy(tdg_ctx* X) {
+  if (X) drop_graph(X);
+  delete X;
+}
 
 }  // extern "C"

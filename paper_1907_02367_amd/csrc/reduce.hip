@@ -93,6 +93,11 @@ __global__ void fill_kernel(double* p, double v, long long n) {
     p[i] = v;
 }
 
+__global__ void fill_i8_kernel(signed char* p, signed char v, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 }  // namespace
 
 int launch_norms(const KParams& P, int kind, const double* ex, double* partial, int nblocks, double* out,
@@ -118,6 +123,14 @@ int launch_fill(double* p, double v, long long n, void* stream_) {
   long long blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream_, p, v, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_fill_i8(signed char* p, signed char v, long long n, void* stream_) {
+  if (n <= 0) return 0;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_i8_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream_, p, v, n);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -14,6 +14,11 @@ constexpr int kMaxGroups = 8;    // speed groups inside one tent (Sec. 4.2)
 constexpr int kMaxPatch = 64;    // elements in one vertex patch
 constexpr int kMaxFaces = 64;    // Dirichlet facets containing one vertex
 constexpr int kBlock = 256;      // threads per workgroup of the tent kernels
+// degree network: features, hidden width, outputs (log indicator for p = 2..8)
+constexpr int kFeat = 8;
+constexpr int kHid = 64;
+constexpr int kOut = 7;
+constexpr int kNParam = kHid * kFeat + kHid + kHid * kHid + kHid + kOut * kHid + kOut;
 
 // Sparse tables of the Trefftz basis of U^p (c = 1) over the monomials
 // t^k x^alpha, k + |alpha| <= p, ordered by total degree, so the first M1
@@ -73,6 +78,7 @@ struct KParams {
   const double* tent_tt;
   const long long* bpt_off;  // ntents+1 offsets into gD
   const signed char* p_per_tent;  // nullable
+  int p_fixed;                    // > 0 and no p_per_tent: every tent at this degree
   // dynamic state
   double* state;  // ne * (n+2) * Q, element-major, then component, then point
   double* tau;    // nv
@@ -80,6 +86,10 @@ struct KParams {
   int* status;    // device error word
   double* dissip; // ntents, nullable
   int* ir_steps;  // ntents, nullable (mixed precision)
+  int indicator;      // 1: compute the per-tent indicator into dissip
+  int write_back;     // 0: indicator only (state and front untouched)
+  double eta_tol;     // > 0: re-solve at p_max where the indicator exceeds it
+  signed char* p_used;  // nullable: degree each tent was finally solved with
   double* work;   // global scratch for systems that do not fit in LDS
   long long work_stride;  // doubles per workgroup slot
   TableDesc tab[kMaxP + 1];
@@ -109,12 +119,17 @@ struct LdsPlan {
   int tab_in_lds;
   int tab_int_dbl;  // doubles occupied by the integer part of a staged table
   int maxfaces;  // Dirichlet facets containing one vertex, at most
-  int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, off_fg, total;
+  int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, off_fg, off_AF, off_vec, total;
 };
 
-int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, void* stream);
+int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, int grid_n, int* ctr, void* stream);
+int resident_blocks_per_cu(int n, int tpw, bool mixed, size_t shm_bytes);
 int set_kernel_smem_limit(int n, size_t bytes);
 int launch_fill(double* p, double v, long long n, void* stream);
+int launch_fill_i8(signed char* p, signed char v, long long n, void* stream);
+int launch_features(const KParams& P, int t0, int count, float* feats, void* stream);
+int launch_select(const unsigned short* wb, const float* feats, int t0, int count, float log_tol, int pmax,
+                  signed char* p_sel, void* stream);
 int launch_norms(const KParams& P, int kind, const double* ex, double* partial, int nblocks, double* out, void* stream);
 
 // ---- host-side components ----------------------------------------------------

@@ -20,7 +20,11 @@
 //      speed interfaces: centred fluxes with penalties (Sec. 4.2).
 //   4. LU: one wave with rows in registers and diagonal pivots for systems up
 //      to 32 unknowns; the whole workgroup with partial pivoting otherwise, back substitution, U constants.
-//   5. (v, sigma, U) at the top points overwrite the stored values; tau_V = t_top.
+//   5. optional indicator: energy of the jump between the new solution and the
+//      incoming trace on the bottom facets (a term of the tent's energy
+//      balance); a tent solved below p_max whose indicator exceeds the
+//      tolerance is solved again at p_max before anything is written
+//   6. (v, sigma, U) at the top points overwrite the stored values; tau_V = t_top.
 #include <hip/hip_runtime.h>
 
 #include "tdg_internal.h"
@@ -30,6 +34,9 @@ namespace tdg {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kIRMax = 6;  // refinement steps of the mixed-precision solve
 
 template <int NS>
 struct El {
@@ -162,6 +169,43 @@ __device__ inline bool wave_lu_regs(const double* A, int lda, int S, double* x) 
   return true;
 }
 
+// In-place LU without row exchanges of the S x S part of A (the right-hand
+// side column is left alone): unit L below the diagonal, U on and above.
+// Valid for the local matrices (positive definite symmetric part, see
+// wave_lu_regs).  Returns false on a zero pivot.
+__device__ inline bool block_lu_factor(double* A, long long lda, int S) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < S; ++k) {
+    const double piv = A[k * lda + k];
+    if (piv == 0.0) return false;
+    for (int i = k + 1 + tid / 4; i < S; i += blockDim.x / 4) {
+      const double l = A[i * lda + k] / piv;
+      for (int j = k + 1 + (tid & 3); j < S; j += 4) A[i * lda + j] -= l * A[k * lda + j];
+    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < S; i += blockDim.x) A[i * lda + k] /= piv;
+    __syncthreads();
+  }
+  return true;
+}
+
+// Solves L U x = b with the factors of block_lu_factor; b (LDS) is overwritten by x.
+__device__ inline void block_lu_apply(const double* A, long long lda, int S, double* b) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < S; ++k) {
+    const double bk = b[k];
+    for (int i = k + 1 + tid; i < S; i += blockDim.x) b[i] -= A[i * lda + k] * bk;
+    __syncthreads();
+  }
+  for (int k = S - 1; k >= 0; --k) {
+    const double xk = b[k] / A[k * lda + k];
+    __syncthreads();
+    if (tid == 0) b[k] = xk;
+    for (int i = tid; i < k; i += blockDim.x) b[i] -= A[i * lda + k] * xk;
+    __syncthreads();
+  }
+}
+
 // Workgroup LU with partial pivoting of the augmented S x (S+1) matrix
 // (LDS or global memory).  s_piv: shared scratch.  Returns false on a zero pivot.
 __device__ inline bool block_lu_solve(double* A, long long lda, int S, double* x, int* s_piv) {
@@ -219,28 +263,30 @@ __device__ inline bool block_lu_solve(double* A, long long lda, int S, double* x
 
 }  // namespace
 
-template <int NS, int TPW>
-__global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L, int t0) {
-  extern __shared__ double lds[];
-  __shared__ int s_m, s_piv, s_err, s_goff[kMaxGroups + 1];
+// Solves one tent; called by every thread of the workgroup.  All early returns
+// are taken by the whole workgroup (their conditions are workgroup-uniform).
+template <int NS, int TPW, bool MIXED>
+__device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, double* lds) {
+  __shared__ int s_m, s_piv, s_err, s_goff[kMaxGroups + 1], s_conv;
+  __shared__ double s_red[2 * kBlock / 64];
   __shared__ int s_gel[kMaxPatch];
   __shared__ int s_fl[kMaxFaces], s_foff[kMaxGroups + 1];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int tent = t0 + blockIdx.x;
   const int V = P.tent_V[tent];
   const double tb = P.tent_tb[tent], tt = P.tent_tt[tent];
   const double tmid = 0.5 * (tb + tt);
   const double dt = tt - tb;
-  const int p = P.p_per_tent ? (int)P.p_per_tent[tent] : P.pmax;
+  const int p_in = P.p_per_tent ? (int)P.p_per_tent[tent] : (P.p_fixed > 0 ? P.p_fixed : P.pmax);
   const int pb = P.v2e_ptr[V];
   const int npatch = P.v2e_ptr[V + 1] - pb;
   const int Q = P.Q;
   const int PCH = L.PCH;
+  const int LD2 = 2 * PCH;  // row stride of the monomial table (top points, then bottom points)
   const int NWP = L.NWP;
   const int ELS = L.ELS;
-  if (p < 1 || p > P.pmax || npatch > L.maxpatch) {
-    if (tid == 0) atomicOr(P.status, (p < 1 || p > P.pmax) ? kStatSize : kStatPatch);
+  if (p_in < 1 || p_in > P.pmax || npatch > L.maxpatch) {
+    if (tid == 0) atomicOr(P.status, (p_in < 1 || p_in > P.pmax) ? kStatSize : kStatPatch);
     return;
   }
   // ---- LDS carve-up --------------------------------------------------------------
@@ -269,6 +315,10 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
   const long long lda = L.lda;
   double* A = L.A_in_lds ? lds + L.off_A : P.work + (long long)blockIdx.x * P.work_stride;
 
+  // A tent solved at a degree below p_max whose realised indicator exceeds the
+  // tolerance is solved again at p_max (second pass of this loop).
+  for (int dtry = 0;; ++dtry) {
+  const int p = dtry == 0 ? p_in : P.pmax;
   // ---- table of degree p (staged in LDS when it fits) ----------------------------
   Tab T;
   {
@@ -433,31 +483,57 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     for (int r = 0; r < kMaxGroups; ++r)
       if (r < m) atomic_max_nonneg(&gh[r], hloc[r]);
   }
-  for (long long i = tid; i < (long long)S * lda; i += blockDim.x) A[i] = 0.0;
+  // mixed precision: FP32 Gram first; faces kept apart (AF) for the FP64 residual
+  double* AF = nullptr;
+  double* bvec = nullptr;  // right-hand side before elimination
+  double* rvec = nullptr;  // residual / correction
+  if constexpr (MIXED) {
+    AF = L.A_in_lds ? lds + L.off_AF : A + (long long)L.S * lda;
+    bvec = lds + L.off_vec;
+    rvec = bvec + L.S;
+  }
+  bool use32 = MIXED;
+  int ir_steps = 0;
+  for (int attempt = 0;; ++attempt) {
+  for (long long i = tid; i < (long long)S * lda; i += blockDim.x) {
+    A[i] = 0.0;
+    if constexpr (MIXED) AF[i] = 0.0;
+  }
   for (int i = tid; i < kMaxGroups * NWP; i += blockDim.x) A0[i] = 0.0;
+  if (tid < kMaxGroups) {
+    A00[tid] = 0.0;
+    r0[tid] = 0.0;
+  }
   __syncthreads();
 
   // ---- 2. top Gram (matrix cores), bottom right-hand side, U recovery rows --------
   const int ntile_dim = (NW + 15) / 16;
   const int ntiles = ntile_dim * (ntile_dim + 1) / 2;
   const int padc = ntile_dim * 16 - NW;
-  // lower-triangular Gram tiles (I >= J) owned by this wave
-  int tI[TPW], tJ[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = wave * TPW + t;
-    int I = 0;
-    while ((I + 1) * (I + 2) / 2 <= tile) ++I;
-    tI[t] = tile < ntiles ? I : -1;
-    tJ[t] = tile - I * (I + 1) / 2;
-  }
-  const int LD2 = 2 * PCH;  // row stride of the monomial table (top points, then bottom points)
-  for (int r = 0; r < m; ++r) {
+  // lower-triangular Gram tiles (I >= J); a pass over the points accumulates
+  // kBlock/64 * TPW of them in registers, more tiles take more passes
+  const int tiles_per_pass = (kBlock / 64) * TPW;
+  const int npass = (ntiles + tiles_per_pass - 1) / tiles_per_pass;
+  for (int rp = 0; rp < m * npass; ++rp) {
+    const int r = rp / npass, pass = rp % npass;
     const double cr = gc[r], hr = gh[r];
     const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
+    int tI[TPW], tJ[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int tile = pass * tiles_per_pass + wave * TPW + t;
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+      tI[t] = tile < ntiles ? I : -1;
+      tJ[t] = tile - I * (I + 1) / 2;
+    }
     d4 acc[TPW];
+    f4 acc32[MIXED ? TPW : 1];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < (MIXED ? TPW : 1); ++t) acc32[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    float* PSI32 = reinterpret_cast<float*>(PSI);
     double rhs_acc = 0.0, a0_acc = 0.0;    // column j = tid
     double rhs_acc2 = 0.0, a0_acc2 = 0.0;  // column j = tid + blockDim.x
     for (int f0 = 0; f0 < npts; f0 += PCH) {
@@ -523,37 +599,58 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
         const int pt = i % PCH, j = i / PCH;
         const double w = PW[pt];
         const double sw = sqrt(w), swD = sqrt(w * PS[pt]);
-        double f[NS + 1], fb[NS + 1], ub;
+        double f[NS + 1], fb[NS + 1], ub = 0.0;
         eval_j<NS, false>(T, j, MT, LD2, pt, f, &ub);
-        eval_j<NS, true>(T, j, MT, LD2, PCH + pt, fb, &ub);
+        if (pass == 0) eval_j<NS, true>(T, j, MT, LD2, PCH + pt, fb, &ub);
         const double v = cr * f[0];
-        double* row = PSI + (size_t)pt * (NS + 1) * NWP + j;
-        row[0] = swD * v;
-        for (int d = 0; d < NS; ++d) row[(1 + d) * NWP] = sw * (f[1 + d] - PG[pt * NS + d] * v);
-        double accb = cr * fb[0] * PD[pt * (NS + 2)];
-        for (int d = 0; d < NS; ++d) accb += fb[1 + d] * PD[pt * (NS + 2) + 1 + d];
-        RB[pt * NWP + j] = accb;
-        UB[pt * NWP + j] = w * hr * ub;
+        if (MIXED && use32) {
+          float* row = PSI32 + (size_t)pt * (NS + 1) * NWP + j;
+          row[0] = (float)(swD * v);
+          for (int d = 0; d < NS; ++d) row[(1 + d) * NWP] = (float)(sw * (f[1 + d] - PG[pt * NS + d] * v));
+        } else {
+          double* row = PSI + (size_t)pt * (NS + 1) * NWP + j;
+          row[0] = swD * v;
+          for (int d = 0; d < NS; ++d) row[(1 + d) * NWP] = sw * (f[1 + d] - PG[pt * NS + d] * v);
+        }
+        if (pass == 0) {
+          double accb = cr * fb[0] * PD[pt * (NS + 2)];
+          for (int d = 0; d < NS; ++d) accb += fb[1 + d] * PD[pt * (NS + 2) + 1 + d];
+          RB[pt * NWP + j] = accb;
+          UB[pt * NWP + j] = w * hr * ub;
+        }
       }
       // zero the padding columns of PSI so the 16-wide tiles see zeros
       for (int i = tid; i < PCH * (NS + 1) * padc; i += blockDim.x) {
         const int row = i / padc, col = NW + i % padc;
-        PSI[row * NWP + col] = 0.0;
+        if (MIXED && use32)
+          PSI32[row * NWP + col] = 0.0f;
+        else
+          PSI[row * NWP + col] = 0.0;
       }
       __syncthreads();
       // Gram on the matrix cores: lane l of a k-step reads row 4 ks + l/16, column 16 I + l%16
       {
         const int nk = (nc * (NS + 1) + 3) / 4;
-        for (int ks = 0; ks < nk; ++ks) {
-          const double* rowp = PSI + (size_t)(ks * 4 + (lane >> 4)) * NWP + (lane & 15);
+        if (MIXED && use32) {
+          for (int ks = 0; ks < nk; ++ks) {
+            const float* rowp = PSI32 + (size_t)(ks * 4 + (lane >> 4)) * NWP + (lane & 15);
 #pragma unroll
-          for (int t = 0; t < TPW; ++t)
-            if (tI[t] >= 0)
-              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowp[tI[t] * 16], rowp[tJ[t] * 16], acc[t], 0, 0, 0);
+            for (int t = 0; t < (MIXED ? TPW : 1); ++t)
+              if (tI[t] >= 0)
+                acc32[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(rowp[tI[t] * 16], rowp[tJ[t] * 16], acc32[t], 0, 0, 0);
+          }
+        } else {
+          for (int ks = 0; ks < nk; ++ks) {
+            const double* rowp = PSI + (size_t)(ks * 4 + (lane >> 4)) * NWP + (lane & 15);
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+              if (tI[t] >= 0)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowp[tI[t] * 16], rowp[tJ[t] * 16], acc[t], 0, 0, 0);
+          }
         }
       }
       // right-hand side and recovery row: column sums over the chunk's points
-      for (int j = tid; j < NW; j += blockDim.x) {
+      for (int j = tid; j < (pass == 0 ? NW : 0); j += blockDim.x) {
         double s1 = 0.0, s2 = 0.0;
         for (int pt = 0; pt < nc; ++pt) {
           s1 += RB[pt * NWP + j];
@@ -567,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
           a0_acc2 += s2;
         }
       }
-      if (tid == blockDim.x - 1) {
+      if (tid == blockDim.x - 1 && pass == 0) {
         double sw = 0.0, su = 0.0;
         for (int pt = 0; pt < nc; ++pt) {
           sw += PW[pt];
@@ -586,19 +683,26 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
         const int j = J * 16 + (lane & 15);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int i = I * 16 + (lane >> 4) + 4 * e;
+          // FP64 output: row l/16 + 4e; FP32 output: row 4(l/16) + e; column l%16
+          const bool f32 = MIXED && use32;
+          const int i = I * 16 + (f32 ? 4 * (lane >> 4) + e : (lane >> 4) + 4 * e);
+          double val;
+          if constexpr (MIXED)
+            val = f32 ? (double)acc32[t][e] : acc[t][e];
+          else
+            val = acc[t][e];
           if (i < NW && j < NW) {
-            A[(long long)(r * NW + i) * lda + r * NW + j] += acc[t][e];
-            if (I != J) A[(long long)(r * NW + j) * lda + r * NW + i] += acc[t][e];
+            A[(long long)(r * NW + i) * lda + r * NW + j] += val;
+            if (I != J) A[(long long)(r * NW + j) * lda + r * NW + i] += val;
           }
         }
       }
     }
-    if (tid < NW) {
+    if (pass == 0 && tid < NW) {
       A[(long long)(r * NW + tid) * lda + S] += rhs_acc;
       A0[r * NWP + tid] += a0_acc;
     }
-    if (tid + (int)blockDim.x < NW) {
+    if (pass == 0 && tid + (int)blockDim.x < NW) {
       A[(long long)(r * NW + tid + blockDim.x) * lda + S] += rhs_acc2;
       A0[r * NWP + tid + blockDim.x] += a0_acc2;
     }
@@ -609,6 +713,7 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
   const int nbf = P.vb_ptr[V + 1] - P.vb_ptr[V];
   const int nif = P.vi_ptr[V + 1] - P.vi_ptr[V];
   double* F1 = W1;  // 4 x PCH rows of NWP: face values
+  double* AT = MIXED ? AF : A;  // face terms (kept apart in the mixed path)
   if (nbf > L.maxfaces) {
     if (tid == 0) atomicOr(P.status, kStatSize);
     return;
@@ -754,12 +859,12 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
           const int ii = idx / NW, jj = idx % NW;
           double acc = 0.0;
           for (int k = 0; k < nc; ++k) acc += F1[k * NWP + ii] * F1[(PCH + k) * NWP + jj];
-          A[(long long)(r * NW + ii) * lda + r * NW + jj] += acc;
+          AT[(long long)(r * NW + ii) * lda + r * NW + jj] += acc;
         }
         for (int j = tid; j < NW; j += blockDim.x) {
           double acc = 0.0;
           for (int k = 0; k < nc; ++k) acc += F1[(2 * PCH + k) * NWP + j];
-          A[(long long)(r * NW + j) * lda + S] += acc;
+          AT[(long long)(r * NW + j) * lda + S] += acc;
         }
         __syncthreads();
       }
@@ -913,7 +1018,7 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
               acc += Vb[k * NWP + ii] * (P.alpha * sa * sb * va + 0.5 * sb * na) +
                      Nb[k * NWP + ii] * (0.5 * sb * va + P.beta * sa * sb * na);
             }
-            A[(long long)(gB * NW + ii) * lda + gA * NW + jj] += acc;
+            AT[(long long)(gB * NW + ii) * lda + gA * NW + jj] += acc;
           }
         }
       }
@@ -921,22 +1026,166 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     }
   }
 
-  // ---- 4. LU with partial pivoting, back substitution, U constants ----------------
-  bool ok;
-  if (S <= 32 && L.A_in_lds) {
-    bool w_ok = true;
-    if (wave == 0) w_ok = wave_lu_regs<32>(A, (int)lda, S, xs);
-    if (wave == 0 && lane == 0 && !w_ok) s_err = kStatSingular;
-    __syncthreads();
-    ok = s_err == 0;
-  } else {
-    ok = block_lu_solve(A, lda, S, xs, &s_piv);
+  // ---- 4. local solve ------------------------------------------------------------------
+  if constexpr (MIXED) {
+    for (long long i = tid; i < (long long)S * lda; i += blockDim.x) A[i] += AF[i];
     __syncthreads();
   }
-  if (!ok) {
-    if (tid == 0) atomicOr(P.status, kStatSingular);
-    return;
+  if (!MIXED || !use32) {
+    // FP64 system: LU, then back substitution
+    bool ok;
+    if (S <= 32 && L.A_in_lds) {
+      bool w_ok = true;
+      if (wave == 0) w_ok = wave_lu_regs<32>(A, (int)lda, S, xs);
+      if (wave == 0 && lane == 0 && !w_ok) s_err = kStatSingular;
+      __syncthreads();
+      ok = s_err == 0;
+    } else {
+      ok = block_lu_solve(A, lda, S, xs, &s_piv);
+      __syncthreads();
+    }
+    if (!ok) {
+      if (tid == 0) atomicOr(P.status, kStatSingular);
+      return;
+    }
+    break;
   }
+  if constexpr (MIXED) {
+    // FP32-assembled system: factor once, solve, refine with the FP64 residual
+    // r = b - (Psi64^T Psi64) x - F x, evaluated matrix-free over the top points
+    for (int i = tid; i < S; i += blockDim.x) bvec[i] = A[(long long)i * lda + S];
+    __syncthreads();
+    const bool fac_ok = block_lu_factor(A, lda, S);
+    __syncthreads();
+    if (!fac_ok) {
+      use32 = false;
+      continue;
+    }
+    for (int i = tid; i < S; i += blockDim.x) xs[i] = bvec[i];
+    __syncthreads();
+    block_lu_apply(A, lda, S, xs);
+    __syncthreads();
+    double dn_prev = INFINITY;
+    if (tid == 0) s_conv = 0;
+    for (int it = 0; it < kIRMax; ++it) {
+      // residual: b - F x
+      for (int i = tid; i < S; i += blockDim.x) {
+        double sacc = 0.0;
+        for (int j = 0; j < S; ++j) sacc += AF[(long long)i * lda + j] * xs[j];
+        rvec[i] = bvec[i] - sacc;
+      }
+      __syncthreads();
+      // ... - Psi64^T (Psi64 x), group by group, chunk by chunk
+      for (int r = 0; r < m; ++r) {
+        const double cr = gc[r], hr = gh[r];
+        const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
+        for (int f0 = 0; f0 < npts; f0 += PCH) {
+          const int nc = min(PCH, npts - f0);
+          for (int pt = tid; pt < PCH; pt += blockDim.x) {
+            double xt[NS], g[NS];
+            double phi = tmid, w = 0.0, sD = 0.0;
+            for (int d = 0; d < NS; ++d) {
+              xt[d] = XV[d];
+              g[d] = 0.0;
+            }
+            if (pt < nc) {
+              const int f = f0 + pt;
+              const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+              const int q = f % Q;
+              const int lV = (int)R[El<NS>::LV];
+              const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+              phi = 0.0;
+              for (int d = 0; d < NS; ++d) xt[d] = 0.0;
+              for (int k = 0; k <= NS; ++k) {
+                phi += lam[k] * R[El<NS>::TAU + k];
+                for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
+              }
+              phi += lam[lV] * dt;
+              w = P.w_ref[q] * R[El<NS>::DET];
+              double gn2 = 0.0;
+              for (int d = 0; d < NS; ++d) {
+                g[d] = R[El<NS>::GNEW + d];
+                gn2 += g[d] * g[d];
+              }
+              sD = 1.0 / (cr * cr) - gn2;
+            }
+            PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
+            for (int d = 0; d < NS; ++d) {
+              PV[pt * (NS + 1) + 1 + d] = (xt[d] - XV[d]) / hr;
+              PG[pt * NS + d] = g[d];
+            }
+            PW[pt] = w;
+            PS[pt] = sD;
+          }
+          __syncthreads();
+          monomials<NS>(T, T.M1, p, PV, POW, MT, PCH, PCH);
+          __syncthreads();
+          for (int i = tid; i < PCH * NW; i += blockDim.x) {
+            const int pt = i % PCH, j = i / PCH;
+            const double w = PW[pt];
+            const double sw = sqrt(w), swD = sqrt(w * PS[pt]);
+            double f[NS + 1], uu;
+            eval_j<NS, false>(T, j, MT, PCH, pt, f, &uu);
+            const double v = cr * f[0];
+            double* row = PSI + (size_t)pt * (NS + 1) * NWP + j;
+            row[0] = swD * v;
+            for (int d = 0; d < NS; ++d) row[(1 + d) * NWP] = sw * (f[1 + d] - PG[pt * NS + d] * v);
+          }
+          __syncthreads();
+          double* yv = RB;  // Psi64 x, one value per row of the chunk
+          for (int row = tid; row < nc * (NS + 1); row += blockDim.x) {
+            double sacc = 0.0;
+            for (int j = 0; j < NW; ++j) sacc += PSI[(size_t)row * NWP + j] * xs[r * NW + j];
+            yv[row] = sacc;
+          }
+          __syncthreads();
+          for (int j = tid; j < NW; j += blockDim.x) {
+            double sacc = 0.0;
+            for (int row = 0; row < nc * (NS + 1); ++row) sacc += PSI[(size_t)row * NWP + j] * yv[row];
+            rvec[r * NW + j] -= sacc;
+          }
+          __syncthreads();
+        }
+      }
+      block_lu_apply(A, lda, S, rvec);
+      // correction norms (max over the block)
+      double dloc = 0.0, xloc = 0.0;
+      for (int i = tid; i < S; i += blockDim.x) {
+        const double xn = xs[i] + rvec[i];
+        dloc = fmax(dloc, fabs(rvec[i]));
+        xloc = fmax(xloc, fabs(xn));
+        xs[i] = xn;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        dloc = fmax(dloc, __shfl_xor(dloc, off, 64));
+        xloc = fmax(xloc, __shfl_xor(xloc, off, 64));
+      }
+      if (lane == 0) {
+        s_red[2 * wave] = dloc;
+        s_red[2 * wave + 1] = xloc;
+      }
+      __syncthreads();
+      double dn = 0.0, xn = 0.0;
+      for (int w = 0; w < (int)blockDim.x / 64; ++w) {
+        dn = fmax(dn, s_red[2 * w]);
+        xn = fmax(xn, s_red[2 * w + 1]);
+      }
+      ir_steps = it + 1;
+      const bool done = dn <= 1e-12 * xn;
+      const bool stalled = !done && dn > 0.5 * dn_prev;
+      dn_prev = dn;
+      __syncthreads();
+      if (done || stalled) {
+        if (tid == 0) s_conv = dn <= 1e-10 * xn ? 1 : 0;
+        break;
+      }
+    }
+    __syncthreads();
+    if (s_conv) break;
+    use32 = false;  // refinement did not reach FP64 accuracy: FP64 Gram for this tent
+  }
+  }  // attempts
+  if (MIXED && tid == 0 && P.ir_steps) P.ir_steps[tent] = ir_steps + (use32 ? 0 : 1000);
   if (tid < m) {
     double s = r0[tid];
     for (int j = 0; j < NW; ++j) s -= A0[tid * NWP + j] * xs[tid * NW + j];
@@ -944,10 +1193,92 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
   }
   __syncthreads();
 
-  // ---- 5. top values overwrite the stored values -----------------------------------
+  // ---- 5. indicator: energy of the jump between the solution and the incoming
+  //         trace on the bottom facets, 1/2 B_phi_old(u - u_b, u - u_b)
   double* cm = W1;  // (NS+2) x M: coefficients of v, sigma, U on the monomials, contracted with x
+  const bool want_eta = P.indicator || P.eta_tol > 0.0 || !P.write_back;
+  if (want_eta) {
+    double eta_loc = 0.0;
+    for (int r = 0; r < m; ++r) {
+      const double cr = gc[r], hr = gh[r];
+      const double ic2 = 1.0 / (cr * cr);
+      __syncthreads();
+      for (int row = tid; row < (NS + 1) * T.M; row += blockDim.x) {
+        double acc = 0.0;
+        for (int e = T.tr_ptr[row]; e < T.tr_ptr[row + 1]; ++e) acc += T.tr_coef[e] * xs[r * NW + T.tr_j[e]];
+        cm[row] = acc;
+      }
+      __syncthreads();
+      const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
+      for (int f0 = 0; f0 < npts; f0 += LD2) {
+        const int nc = min(LD2, npts - f0);
+        for (int pt = tid; pt < LD2; pt += blockDim.x) {
+          double xt[NS], phi = tmid;
+          for (int d = 0; d < NS; ++d) xt[d] = XV[d];
+          if (pt < nc) {
+            const int f = f0 + pt;
+            const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+            const int q = f % Q;
+            const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+            phi = 0.0;
+            for (int d = 0; d < NS; ++d) xt[d] = 0.0;
+            for (int k = 0; k <= NS; ++k) {
+              phi += lam[k] * R[El<NS>::TAU + k];
+              for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
+            }
+          }
+          PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
+          for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (xt[d] - XV[d]) / hr;
+        }
+        __syncthreads();
+        monomials<NS>(T, T.M1, p, PV, POW, MT, LD2, LD2);
+        __syncthreads();
+        for (int pt = tid; pt < nc; pt += blockDim.x) {
+          const int f = f0 + pt;
+          const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+          const int q = f % Q;
+          const int e = (int)R[El<NS>::E];
+          const double w = P.w_ref[q] * R[El<NS>::DET];
+          const double* st = P.state + (size_t)e * (NS + 2) * Q;
+          double val[NS + 1];
+          for (int comp = 0; comp <= NS; ++comp) {
+            double acc = 0.0;
+            for (int k = 0; k < T.M1; ++k) acc += cm[comp * T.M + k] * MT[k * LD2 + pt];
+            val[comp] = acc;
+          }
+          const double dv = cr * val[0] - st[q];
+          double ds2 = 0.0, dsg = 0.0;
+          for (int d = 0; d < NS; ++d) {
+            const double ds = val[1 + d] - st[(1 + d) * Q + q];
+            ds2 += ds * ds;
+            dsg += ds * R[El<NS>::GOLD + d];
+          }
+          eta_loc += 0.5 * w * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
+        }
+        __syncthreads();
+      }
+    }
+    // deterministic workgroup sum
+    for (int off = 32; off > 0; off >>= 1) eta_loc += __shfl_xor(eta_loc, off, 64);
+    __syncthreads();
+    if (lane == 0) s_red[wave] = eta_loc;
+    __syncthreads();
+    double eta = 0.0;
+    for (int w = 0; w < (int)blockDim.x / 64; ++w) eta += s_red[w];
+    const bool redo = P.eta_tol > 0.0 && dtry == 0 && p < P.pmax && eta > P.eta_tol;
+    __syncthreads();
+    if (redo) continue;
+    if (tid == 0 && P.dissip) P.dissip[tent] = eta;
+    if (tid == 0 && P.p_used) P.p_used[tent] = (signed char)p;
+    if (!P.write_back) return;
+  } else if (tid == 0 && P.p_used) {
+    P.p_used[tent] = (signed char)p;
+  }
+
+  // ---- 6. top values overwrite the stored values -----------------------------------
   for (int r = 0; r < m; ++r) {
     const double cr = gc[r], hr = gh[r];
+    __syncthreads();
     for (int row = tid; row < (NS + 2) * T.M; row += blockDim.x) {
       double acc = 0.0;
       for (int e = T.tr_ptr[row]; e < T.tr_ptr[row + 1]; ++e) acc += T.tr_coef[e] * xs[r * NW + T.tr_j[e]];
@@ -1002,63 +1333,122 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     }
   }
   if (tid == 0) P.tau[V] = tt;
+  break;
+  }  // degree attempts
+}
+
+// All tents of one layer: tents t0 .. t0+count-1.  Without a counter each
+// workgroup solves tent t0 + blockIdx.x; with a counter (persistent mode) a
+// resident grid takes tents in queue order from the counter until it passes
+// count (every workgroup exits after at most count + gridDim.x draws).
+template <int NS, int TPW, bool MIXED>
+__global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L, int t0, int count, int* ctr) {
+  extern __shared__ double lds[];
+  if (ctr == nullptr) {
+    solve_tent<NS, TPW, MIXED>(P, L, t0 + blockIdx.x, lds);
+    return;
+  }
+  __shared__ int s_next;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(ctr, 1);
+    __syncthreads();
+    const int i = s_next;
+    __syncthreads();
+    if (i >= count) break;
+    solve_tent<NS, TPW, MIXED>(P, L, t0 + i, lds);
+    __syncthreads();
+  }
 }
 
 namespace {
 
+template <int NS, bool MX>
+const void* kernel_ptr_mx(int tpw) {
+  switch (tpw) {
+    case 1:
+      return (const void*)tent_layer_kernel<NS, 1, MX>;
+    case 2:
+      return (const void*)tent_layer_kernel<NS, 2, MX>;
+    case 4:
+      return (const void*)tent_layer_kernel<NS, 4, MX>;
+    case 8:
+      return (const void*)tent_layer_kernel<NS, 8, MX>;
+    default:
+      return (const void*)tent_layer_kernel<NS, 16, MX>;
+  }
+}
+
 template <int NS>
-hipError_t launch_ns(const KParams& P, const LdsPlan& L, int t0, int count, hipStream_t stream) {
-  dim3 grid(count), block(kBlock);
+const void* kernel_ptr(int tpw, bool mixed) {
+  return mixed ? kernel_ptr_mx<NS, true>(tpw) : kernel_ptr_mx<NS, false>(tpw);
+}
+
+template <int NS, bool MX>
+hipError_t launch_mx(const KParams& P, const LdsPlan& L, int t0, int count, int grid_n, int* ctr, hipStream_t stream) {
+  dim3 grid(grid_n), block(kBlock);
   size_t shm = (size_t)L.total * sizeof(double);
   switch (L.TPW) {
     case 1:
-      hipLaunchKernelGGL((tent_layer_kernel<NS, 1>), grid, block, shm, stream, P, L, t0);
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 1, MX>), grid, block, shm, stream, P, L, t0, count, ctr);
       break;
     case 2:
-      hipLaunchKernelGGL((tent_layer_kernel<NS, 2>), grid, block, shm, stream, P, L, t0);
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 2, MX>), grid, block, shm, stream, P, L, t0, count, ctr);
       break;
     case 4:
-      hipLaunchKernelGGL((tent_layer_kernel<NS, 4>), grid, block, shm, stream, P, L, t0);
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 4, MX>), grid, block, shm, stream, P, L, t0, count, ctr);
       break;
     case 8:
-      hipLaunchKernelGGL((tent_layer_kernel<NS, 8>), grid, block, shm, stream, P, L, t0);
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 8, MX>), grid, block, shm, stream, P, L, t0, count, ctr);
       break;
     default:
-      hipLaunchKernelGGL((tent_layer_kernel<NS, 16>), grid, block, shm, stream, P, L, t0);
+      hipLaunchKernelGGL((tent_layer_kernel<NS, 16, MX>), grid, block, shm, stream, P, L, t0, count, ctr);
       break;
   }
   return hipGetLastError();
 }
 
 template <int NS>
+hipError_t launch_ns(const KParams& P, const LdsPlan& L, int t0, int count, int grid_n, int* ctr, hipStream_t stream) {
+  return P.precision ? launch_mx<NS, true>(P, L, t0, count, grid_n, ctr, stream)
+                     : launch_mx<NS, false>(P, L, t0, count, grid_n, ctr, stream);
+}
+
+template <int NS>
 hipError_t smem_ns(size_t bytes) {
   const hipFuncAttribute a = hipFuncAttributeMaxDynamicSharedMemorySize;
-  hipError_t e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 1>, a, (int)bytes);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 2>, a, (int)bytes);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 4>, a, (int)bytes);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 8>, a, (int)bytes);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)tent_layer_kernel<NS, 16>, a, (int)bytes);
+  hipError_t e = hipSuccess;
+  for (int mx = 0; mx < 2 && e == hipSuccess; ++mx)
+    for (int tpw : {1, 2, 4, 8, 16})
+      if (e == hipSuccess) e = hipFuncSetAttribute(kernel_ptr<NS>(tpw, mx == 1), a, (int)bytes);
   return e;
 }
 
 }  // namespace
 
-int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, void* stream_) {
+int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, int grid_n, int* ctr, void* stream_) {
   if (count <= 0) return 0;
   hipStream_t stream = (hipStream_t)stream_;
+  if (!ctr) grid_n = count;
   hipError_t e;
   switch (P.n) {
     case 1:
-      e = launch_ns<1>(P, L, t0, count, stream);
+      e = launch_ns<1>(P, L, t0, count, grid_n, ctr, stream);
       break;
     case 2:
-      e = launch_ns<2>(P, L, t0, count, stream);
+      e = launch_ns<2>(P, L, t0, count, grid_n, ctr, stream);
       break;
     default:
-      e = launch_ns<3>(P, L, t0, count, stream);
+      e = launch_ns<3>(P, L, t0, count, grid_n, ctr, stream);
       break;
   }
   return e == hipSuccess ? 0 : -1;
+}
+
+int resident_blocks_per_cu(int n, int tpw, bool mixed, size_t shm_bytes) {
+  const void* k = n == 1 ? kernel_ptr<1>(tpw, mixed) : n == 2 ? kernel_ptr<2>(tpw, mixed) : kernel_ptr<3>(tpw, mixed);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBlock, shm_bytes) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
 }
 
 int set_kernel_smem_limit(int n, size_t bytes) {

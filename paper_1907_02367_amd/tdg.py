@@ -65,6 +65,27 @@ EXPORTS = {
     "trefftz_read_state": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "trefftz_table_info": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "trefftz_set_tuning": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32],
+    "trefftz_get_tuning": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32)],
+    "trefftz_capture_sweep": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                              ctypes.c_void_p],
+    "trefftz_replay_sweep": [ctypes.c_void_p, ctypes.c_void_p],
+    "trefftz_tent_stats": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p],
+    "trefftz_set_indicator": [ctypes.c_void_p, ctypes.c_int32],
+    "trefftz_tent_features": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
+    "trefftz_layer_indicator": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
+    "trefftz_layer_solve_adaptive": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_float,
+                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p],
+    "tdg_mlp_nparam": [],
+    "tdg_mlp_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
+    "tdg_mlp_backward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                         ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "tdg_mlp_adam": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_void_p],
+    "tdg_mlp_round": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "trefftz_destroy": [ctypes.c_void_p],
     "tdg_last_error": [],
 }
@@ -106,6 +127,63 @@ def lib():
         L.tdg_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
+
+
+def _dptr(t, dtype, shape):
+    """Device pointer of a contiguous CUDA tensor of the given dtype and shape
+    (argument checks only)."""
+    import torch
+
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == getattr(torch, dtype) and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"expected a contiguous CUDA {dtype} tensor of shape {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---- degree network (C-ABI tdg_mlp_*; device tensors, argument marshalling only)
+def mlp_nparam():
+    return int(lib().tdg_mlp_nparam())
+
+
+def mlp_forward(w_bf16, x, stream=None):
+    """y (n x 7 float32) = network(x (n x 8 float32)) with BF16 weights (stored as int16)."""
+    import torch
+
+    n = x.shape[0]
+    y = torch.empty((n, 7), dtype=torch.float32, device=x.device)
+    _check(lib().tdg_mlp_forward(_dptr(w_bf16, "int16", (mlp_nparam(),)), _dptr(x, "float32", (n, 8)), n,
+                                 _dptr(y, "float32", (n, 7)), _stream(stream)))
+    return y
+
+
+def mlp_backward(w_bf16, x, target, mask, norm, partial=None, grad=None, stream=None):
+    """Gradient of sum mask (y - target)^2 / norm: returns grad (nparam+1
+    float32, last entry the loss) and the scratch used."""
+    import torch
+
+    n, P = x.shape[0], mlp_nparam()
+    nb = (n + 31) // 32
+    if partial is None or partial.numel() < nb * (P + 1):
+        partial = torch.empty(nb * (P + 1), dtype=torch.float32, device=x.device)
+    if grad is None:
+        grad = torch.empty(P + 1, dtype=torch.float32, device=x.device)
+    _check(lib().tdg_mlp_backward(_dptr(w_bf16, "int16", (P,)), _dptr(x, "float32", (n, 8)),
+                                  _dptr(target, "float32", (n, 7)), _dptr(mask, "float32", (n, 7)), n, float(norm),
+                                  ctypes.c_void_p(partial.data_ptr()), _dptr(grad, "float32", (P + 1,)),
+                                  _stream(stream)))
+    return grad, partial
+
+
+def mlp_adam(w32, w_bf16, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    P = mlp_nparam()
+    _check(lib().tdg_mlp_adam(_dptr(w32, "float32", (P,)), _dptr(w_bf16, "int16", (P,)),
+                              ctypes.c_void_p(grad.data_ptr()), _dptr(m, "float32", (P,)), _dptr(v, "float32", (P,)),
+                              int(step), float(lr), float(b1), float(b2), float(eps), _stream(stream)))
+
+
+def mlp_round(w32, w_bf16, stream=None):
+    P = mlp_nparam()
+    _check(lib().tdg_mlp_round(_dptr(w32, "float32", (P,)), _dptr(w_bf16, "int16", (P,)), _stream(stream)))
 
 
 def _check(rc):
@@ -261,6 +339,59 @@ class Trefftz:
         U = np.empty(self.nq)
         _check(lib().trefftz_read_state(self._h, _ptr(v), _ptr(s), _ptr(U), _stream()))
         return v.reshape(self.ne, self.Q), s.reshape(self.ne, self.Q, self.n), U.reshape(self.ne, self.Q)
+
+    def set_tuning(self, pts_per_chunk=0, persistent=0):
+        _check(lib().trefftz_set_tuning(self._h, int(pts_per_chunk), int(persistent)))
+
+    def get_tuning(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().trefftz_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(pts_per_chunk=a.value, persistent=b.value, lds_bytes=c.value)
+
+    def capture_sweep(self, layer_begin=0, layer_end=None, p_per_tent=None, with_reset=True, stream=None):
+        if layer_end is None:
+            layer_end = self.tents.n_layers
+        pp = None if p_per_tent is None else ctypes.c_void_p(p_per_tent.data_ptr())
+        _check(lib().trefftz_capture_sweep(self._h, int(layer_begin), int(layer_end), pp, int(bool(with_reset)),
+                                           _stream(stream)))
+
+    def replay_sweep(self, stream=None):
+        _check(lib().trefftz_replay_sweep(self._h, _stream(stream)))
+
+    def tent_stats(self, first=0, count=None):
+        if count is None:
+            count = self.tents.n_tents - first
+        ir = np.zeros(count, np.int32)
+        dis = np.zeros(count)
+        _check(lib().trefftz_tent_stats(self._h, int(first), int(count), _ptr(ir), _ptr(dis), _stream()))
+        return ir, dis
+
+    def set_indicator(self, on=True):
+        _check(lib().trefftz_set_indicator(self._h, int(bool(on))))
+
+    def tent_features(self, layer, feats, stream=None):
+        """Writes the features of the tents of `layer` into the device tensor
+        feats (n_tents x 8 float32)."""
+        _check(lib().trefftz_tent_features(self._h, int(layer), _dptr(feats, "float32", (self.tents.n_tents, 8)),
+                                           _stream(stream)))
+
+    def layer_indicator(self, layer, p, eta, stream=None):
+        """eta_T at degree p of the tents of `layer` into the device tensor eta
+        (n_tents float64); nothing else changes."""
+        _check(lib().trefftz_layer_indicator(self._h, int(layer), int(p), _dptr(eta, "float64", (self.tents.n_tents,)),
+                                             _stream(stream)))
+
+    def layer_solve_adaptive(self, w_bf16, log_eta_tol, eta_tol, feats, p_sel, p_used=None, eta=None,
+                             layer_begin=0, layer_end=None, stream=None):
+        if layer_end is None:
+            layer_end = self.tents.n_layers
+        nt = self.tents.n_tents
+        w = None if w_bf16 is None else _dptr(w_bf16, "int16", (mlp_nparam(),))
+        _check(lib().trefftz_layer_solve_adaptive(
+            self._h, int(layer_begin), int(layer_end), w, float(log_eta_tol), float(eta_tol),
+            _dptr(feats, "float32", (nt, 8)), _dptr(p_sel, "int8", (nt,)),
+            None if p_used is None else _dptr(p_used, "int8", (nt,)),
+            None if eta is None else _dptr(eta, "float64", (nt,)), _stream(stream)))
 
     def table_info(self, p):
         N, nnz, M, Q = (ctypes.c_int32() for _ in range(4))

@@ -18,6 +18,13 @@ from workloads import fields as F
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
+# 3D p = 8: the tent systems reach condition number 3.6e17 (median 2.5e15) in
+# the monomial Trefftz basis; the oracle's own result moves by 2.1e-11 under a
+# random one-ulp relative perturbation of its matrix and right-hand side, so a
+# backward-stable solve in another summation order (the matrix-core Gram sums
+# thousands of products per entry) is expected to differ by tens of ulps of
+# backward error: tolerance 50x the one-ulp floor.
+TOL_CASE = {"3d_p8_b_multipass_gram": 1e-9}
 
 
 def say(*a):
@@ -37,6 +44,7 @@ CASES = {
     "2d_p8_m4": lambda: (C.cfg2_plane_2d(m=4, p=8), None, None),
     "3d_p5_b": lambda: (C.cfg5_cube_3d(m=2, p=5, variant="b"), None, None),
     "3d_p3_a_8groups_global_system": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="a", regions=2), None, None),
+    "3d_p8_b_multipass_gram": lambda: (C.cfg5_cube_3d(m=2, p=8, variant="b"), None, None),
 }
 
 
@@ -44,7 +52,7 @@ CASES = {
 def test_full_run_matches_oracle(name):
     pr, field, q = CASES[name]()
     if pr.n == 3:
-        pr.T = 0.25 if pr.p <= 3 else 0.1
+        pr.T = 0.25 if pr.p <= 3 else (0.1 if pr.p <= 5 else 0.03)
     say(f"[gpu parity] {name}: n={pr.n} p={pr.p} ne={len(pr.elems)}")
     o = oracle_for(pr, field, q=q)
     o.run()
@@ -55,7 +63,8 @@ def test_full_run_matches_oracle(name):
     r_vs = rel_l2(np.concatenate([v.ravel(), s.ravel()]), np.concatenate([o.v.ravel(), o.sig.ravel()]))
     r_U = rel_l2(U, o.U)
     say(f"  rel diff (v, sigma) {r_vs:.2e}, U {r_U:.2e}")
-    assert r_vs <= TOL and r_U <= TOL, (r_vs, r_U)
+    tol = TOL_CASE.get(name, TOL)
+    assert r_vs <= tol and r_U <= tol, (r_vs, r_U)
     if pr.exact:
         f = field or pr.data
         X = o.quad_points()
@@ -158,3 +167,78 @@ def test_empty_range_and_invalid_degree():
     with pytest.raises(tdg.TdgError) as ei:
         ctx.status()
     assert ei.value.name == "TDG_EINVAL"
+
+
+@pytest.mark.parametrize("shape", [(16, 0), (32, 1), (64, 1)])
+def test_kernel_shapes_give_the_same_answer(shape):
+    pr = C.cfg2_plane_2d(m=10, p=4)
+    say(f"[gpu parity] kernel shape {shape}")
+    ctx, xq, w = gpu_for(pr)
+    ctx.layer_solve()
+    ref = ctx.read_state()
+    ctx.set_tuning(*shape)
+    ctx.reset()
+    ctx.layer_solve()
+    got = ctx.read_state()
+    ctx.status()
+    for a, b in zip(got, ref):
+        assert rel_l2(a, b) <= 1e-13
+
+
+def test_graph_replays_match_eager():
+    import torch
+
+    pr = C.cfg2_plane_2d(m=10, p=4)
+    say("[gpu parity] graph capture and replay")
+    ctx, xq, w = gpu_for(pr)
+    ctx.layer_solve()
+    ref = ctx.read_state()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx.capture_sweep(0, ctx.tents.n_layers, with_reset=True, stream=s.cuda_stream)
+    for rep in range(3):
+        # eager work between replays
+        ctx.reset()
+        ctx.layer_solve(0, 5)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            ctx.replay_sweep(s.cuda_stream)
+        torch.cuda.synchronize()
+        got = ctx.read_state()
+        for a, b in zip(got, ref):
+            assert rel_l2(a, b) <= 1e-13, rep
+    ctx.status()
+
+
+MIXED_CASES = {
+    "2d_p3_m8": lambda: (C.cfg2_plane_2d(m=8, p=3), None),
+    "2d_p4_m8": lambda: (C.cfg2_plane_2d(m=8, p=4), None),
+    "2d_p6_m6": lambda: (C.cfg2_plane_2d(m=6, p=6), None),
+    "2d_interface_p3": lambda: (C.cfg4_interface_2d(m=9, p=3), None),
+    "3d_p3_b": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="b"), None),
+}
+
+
+@pytest.mark.parametrize("name", list(MIXED_CASES))
+def test_mixed_precision_matches_oracle(name):
+    """FP32 matrix-core Gram + FP64 LU + FP64 refinement (or per-tent FP64
+    fallback) must reach the FP64 bar against the oracle."""
+    pr, field = MIXED_CASES[name]()
+    if pr.n == 3:
+        pr.T = 0.25
+    say(f"[gpu mixed] {name}")
+    o = oracle_for(pr, field)
+    o.run()
+    ctx, xq, w = gpu_for(pr, field, precision=1)
+    ctx.layer_solve()
+    v, s, U = ctx.read_state()
+    ctx.status()
+    ir, _ = ctx.tent_stats()
+    fb = (ir >= 1000).mean()
+    steps = (ir % 1000)
+    r_vs = rel_l2(np.concatenate([v.ravel(), s.ravel()]), np.concatenate([o.v.ravel(), o.sig.ravel()]))
+    r_U = rel_l2(U, o.U)
+    say(f"  rel diff (v, sigma) {r_vs:.2e}, U {r_U:.2e}; refinement steps mean {steps.mean():.2f}, "
+        f"FP64 fallback {100 * fb:.1f} %")
+    assert (steps >= 1).all()
+    assert r_vs <= TOL and r_U <= TOL, (r_vs, r_U)
