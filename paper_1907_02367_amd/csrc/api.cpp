@@ -130,33 +130,73 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
     int min_pch;
   };
   const Choice order[4] = {{true, true, 16}, {true, false, 16}, {false, true, 4}, {false, false, 4}};
+  const int pmax = X->opts.p_max;
+  // per-point sizes (doubles) of the chunk regions at degree p with operand stride nwp
+  auto pow_sz = [&](int p, long long c) { return 2LL * c * (n + 1) * (p + 1); };
+  auto mono_sz = [&](int p, long long c) { return (long long)X->tabs[p].M * 2 * c; };
+  auto w1_sz = [&](int p, long long c) {
+    const long long nwp = ((X->tabs[p].NW + 15) / 16) * 16 + 1;
+    return std::max<long long>(c * (n + 3) * nwp, (long long)(n + 2) * X->tabs[p].M);
+  };
+  const long long pt_per = 2 * (n + 1) + 1 + (n + 2) + n + 1;
+  for (int p = 0; p <= kMaxP; ++p) {
+    L.pch[p] = 0;
+    L.nwp[p] = 0;
+  }
+  for (int p = 1; p <= pmax; ++p) L.nwp[p] = ((X->tabs[p].NW + 15) / 16) * 16 + 1;
   for (const Choice& ch : order) {
     for (int pch : {64, 32, 16, 8, 4}) {
       if (forced_pch ? pch != forced_pch : pch < ch.min_pch) continue;
       L.PCH = pch;
       L.A_in_lds = ch.a;
       L.tab_in_lds = ch.t;
-      int off = 0;
-      auto take = [&](long long cnt) {
-        int o = off;
-        off += (int)((cnt + 3) & ~3LL);
-        return o;
-      };
-      L.off_x = take(L.S + kMaxGroups);
-      L.off_el = take((long long)maxpatch * L.ELS);
-      L.off_misc = take(5 * kMaxGroups + 24 + (long long)kMaxGroups * L.NWP);
-      L.off_pt = take((long long)pch * (2 * (n + 1) + 1 + (n + 2) + n + 1));
-      L.off_pow = take(2LL * pch * (n + 1) * (X->opts.p_max + 1));
-      L.off_mono = take((long long)Tm.M * 2 * pch);
-      L.off_W1 = take(std::max<long long>((long long)pch * (n + 3) * L.NWP, (long long)(n + 2) * Tm.M));
-      L.off_fg = take((long long)std::max(L.maxfaces, 1) * (2 + n + (n + 1) * (n + 1)));
-      L.off_tab = ch.t ? take(tab_dbl) : 0;
-      L.off_A = ch.a ? take((long long)L.S * L.lda) : 0;
-      const bool mixed = X->opts.precision == 1;
-      L.off_AF = (mixed && ch.a) ? take((long long)L.S * L.lda) : 0;
-      L.off_vec = mixed ? take(2LL * L.S) : 0;
-      L.total = off;
-      if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) return TDG_OK;
+      // a lower degree takes the largest chunk whose monomial and operand regions
+      // fit in the ones sized for p_max; the small point and power regions grow
+      // with it while the whole plan fits (else lower degrees shrink back)
+      for (int p = 1; p <= pmax; ++p) {
+        int c = pch;
+        if (p < pmax)
+          for (int cand : {64, 32, 16, 8, 4})
+            if (cand >= pch && mono_sz(p, cand) <= mono_sz(pmax, pch) && w1_sz(p, cand) <= w1_sz(pmax, pch)) {
+              c = cand;
+              break;
+            }
+        L.pch[p] = c;
+      }
+      for (;;) {
+        long long pt_sz = 0, pw_sz = 0;
+        for (int p = 1; p <= pmax; ++p) {
+          pt_sz = std::max(pt_sz, L.pch[p] * pt_per);
+          pw_sz = std::max(pw_sz, pow_sz(p, L.pch[p]));
+        }
+        int off = 0;
+        auto take = [&](long long cnt) {
+          int o = off;
+          off += (int)((cnt + 3) & ~3LL);
+          return o;
+        };
+        L.off_x = take(L.S + kMaxGroups);
+        L.off_el = take((long long)maxpatch * L.ELS);
+        L.off_misc = take(5 * kMaxGroups + 24 + (long long)kMaxGroups * L.NWP);
+        L.off_pt = take(pt_sz);
+        L.off_pow = take(pw_sz);
+        L.off_mono = take(mono_sz(pmax, pch));
+        L.off_W1 = take(w1_sz(pmax, pch));
+        L.off_fg = take((long long)std::max(L.maxfaces, 1) * (2 + n + (n + 1) * (n + 1)));
+        L.off_tab = ch.t ? take(tab_dbl) : 0;
+        L.off_A = ch.a ? take((long long)L.S * L.lda) : 0;
+        const bool mixed = X->opts.precision == 1;
+        L.off_AF = (mixed && ch.a) ? take((long long)L.S * L.lda) : 0;
+        L.off_vec = mixed ? take(2LL * L.S) : 0;
+        L.total = off;
+        if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) return TDG_OK;
+        // shrink the largest lower-degree chunk, if any is above the p_max chunk
+        int pbig = 0;
+        for (int p = 1; p < pmax; ++p)
+          if (L.pch[p] > pch && (pbig == 0 || L.pch[p] > L.pch[pbig])) pbig = p;
+        if (!pbig) break;
+        L.pch[pbig] /= 2;
+      }
     }
   }
   return fail(TDG_EINVAL, "tent kernel working set does not fit in LDS");

@@ -110,7 +110,9 @@ struct LdsPlan {
   int S;         // largest system size (groups * NW)
   int lda;       // row stride of the augmented matrix
   int NWP;       // row stride of the Gram operand (16-padded NW, odd)
-  int PCH;       // points per chunk
+  int PCH;       // points per chunk at p_max
+  int pch[kMaxP + 1];  // points per chunk at each degree (>= PCH below p_max)
+  int nwp[kMaxP + 1];  // Gram operand row stride at each degree
   int M;         // monomials of degree <= p_max
   int TPW;       // Gram tiles per wave
   int maxpatch;

@@ -281,9 +281,6 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   const int pb = P.v2e_ptr[V];
   const int npatch = P.v2e_ptr[V + 1] - pb;
   const int Q = P.Q;
-  const int PCH = L.PCH;
-  const int LD2 = 2 * PCH;  // row stride of the monomial table (top points, then bottom points)
-  const int NWP = L.NWP;
   const int ELS = L.ELS;
   if (p_in < 1 || p_in > P.pmax || npatch > L.maxpatch) {
     if (tid == 0) atomicOr(P.status, (p_in < 1 || p_in > P.pmax) ? kStatSize : kStatPatch);
@@ -300,17 +297,6 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   double* a0 = r0 + kMaxGroups;
   double* fsc = a0 + kMaxGroups;  // 24: face measure, normal, simplex vertices
   double* A0 = fsc + 24;          // kMaxGroups x NWP
-  double* PV = lds + L.off_pt;    // 2*PCH x (NS+1): top then bottom coordinates
-  double* PW = PV + 2 * PCH * (NS + 1);  // PCH weights
-  double* PD = PW + PCH;                 // PCH x (NS+2): weighted bottom data, w*U_b
-  double* PG = PD + PCH * (NS + 2);      // PCH x NS: grad phi_new at the point
-  double* PS = PG + PCH * NS;            // PCH: c^-2 - |g_new|^2
-  double* POW = lds + L.off_pow;         // 2*PCH x (NS+1) x (pmax+1)
-  double* MT = lds + L.off_mono;         // M x 2*PCH monomials (top points, then bottom points)
-  double* W1 = lds + L.off_W1;           // PSI: PCH*(NS+1) rows, RB: PCH rows, UB: PCH rows (row stride NWP)
-  double* PSI = W1;
-  double* RB = W1 + PCH * (NS + 1) * NWP;
-  double* UB = RB + PCH * NWP;
   // system: LDS or this workgroup's slot of the global scratch
   const long long lda = L.lda;
   double* A = L.A_in_lds ? lds + L.off_A : P.work + (long long)blockIdx.x * P.work_stride;
@@ -319,6 +305,21 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   // tolerance is solved again at p_max (second pass of this loop).
   for (int dtry = 0;; ++dtry) {
   const int p = dtry == 0 ? p_in : P.pmax;
+  // chunk size and operand stride of degree p (lower degrees take larger chunks)
+  const int PCH = L.pch[p];
+  const int LD2 = 2 * PCH;  // row stride of the monomial table (top points, then bottom points)
+  const int NWP = L.nwp[p];
+  double* PV = lds + L.off_pt;    // 2*PCH x (NS+1): top then bottom coordinates
+  double* PW = PV + 2 * PCH * (NS + 1);  // PCH weights
+  double* PD = PW + PCH;                 // PCH x (NS+2): weighted bottom data, w*U_b
+  double* PG = PD + PCH * (NS + 2);      // PCH x NS: grad phi_new at the point
+  double* PS = PG + PCH * NS;            // PCH: c^-2 - |g_new|^2
+  double* POW = lds + L.off_pow;         // 2*PCH x (NS+1) x (p+1)
+  double* MT = lds + L.off_mono;         // M x 2*PCH monomials (top points, then bottom points)
+  double* W1 = lds + L.off_W1;           // PSI: PCH*(NS+1) rows, RB: PCH rows, UB: PCH rows (row stride NWP)
+  double* PSI = W1;
+  double* RB = W1 + PCH * (NS + 1) * NWP;
+  double* UB = RB + PCH * NWP;
   // ---- table of degree p (staged in LDS when it fits) ----------------------------
   Tab T;
   {
@@ -1196,7 +1197,7 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   // ---- 5. indicator: energy of the jump between the solution and the incoming
   //         trace on the bottom facets, 1/2 B_phi_old(u - u_b, u - u_b)
   double* cm = W1;  // (NS+2) x M: coefficients of v, sigma, U on the monomials, contracted with x
-  const bool want_eta = P.indicator || P.eta_tol > 0.0 || !P.write_back;
+  const bool want_eta = P.indicator || !P.write_back || (P.eta_tol > 0.0 && dtry == 0 && p < P.pmax);
   if (want_eta) {
     double eta_loc = 0.0;
     for (int r = 0; r < m; ++r) {

@@ -103,7 +103,15 @@ class DegreeNet:
 def make_context(pr, p_max=None, precision=0, device=None):
     """Library context of a workload (synthetic inputs resident on the GPU)."""
     f = pr.data
-    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    gamma = pr.gamma
+    while True:  # a strongly jittered mesh may need a smaller edge-slope factor
+        try:
+            T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, gamma)
+            break
+        except tdg.TdgError as e:
+            if e.name != "TDG_ENONCAUSAL" or gamma < 0.05:
+                raise
+            gamma *= 0.8
     ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max or pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta,
                       precision=precision)
     xq, w = ctx.quad_points()
@@ -114,10 +122,11 @@ def make_context(pr, p_max=None, precision=0, device=None):
     return ctx, xq
 
 
-def collect(ctx, p_list=range(2, 9), layer_stride=1):
+def collect(ctx, p_list=range(2, 9), layer_stride=1, progress=None):
     """Sweeps the context at p_max; before every `layer_stride`-th layer,
     records the features and eta_T(p) for p in p_list of its tents.
-    Returns device tensors X (n x 8), Y = log eta (n x 7), M (n x 7 mask)."""
+    Returns device tensors X (n x 8), Y = log eta (n x 7), M (n x 7 mask).
+    progress(l, L), if given, is called after every tenth layer."""
     torch = _torch()
     nt = ctx.tents.n_tents
     L = ctx.tents.n_layers
@@ -125,15 +134,25 @@ def collect(ctx, p_list=range(2, 9), layer_stride=1):
     feats = torch.zeros((nt, N_FEAT), dtype=torch.float32, device="cuda")
     eta = torch.full((N_OUT, nt), -1.0, dtype=torch.float64, device="cuda")
     taken = torch.zeros(nt, dtype=torch.bool, device="cuda")
-    p_list = [p for p in p_list if 2 <= p <= ctx.p_max]
+    p_list = [p for p in p_list if 2 <= p < ctx.p_max]
+    # eta_T(p_max) comes with the sweep's own solve
+    ctx.set_indicator(True)
+    eta_top = ctx.indicator_tensor()
     for l in range(L):
+        a, b = lp[l], lp[l + 1]
         if l % layer_stride == 0:
             ctx.tent_features(l, feats)
             for p in p_list:
                 ctx.layer_indicator(l, p, eta[p - 2])
-            taken[lp[l]:lp[l + 1]] = True
+            taken[a:b] = True
         ctx.layer_solve(l, l + 1)
+        if l % layer_stride == 0 and ctx.p_max >= 2:
+            eta[ctx.p_max - 2, a:b] = eta_top[a:b]
+        if progress is not None and (l % 10 == 9 or l == L - 1):
+            torch.cuda.synchronize()
+            progress(l + 1, L)
     ctx.status()
+    ctx.set_indicator(False)
     X = feats[taken].contiguous()
     E = eta[:, taken].T.contiguous()
     M = (E > 0) & torch.isfinite(E)

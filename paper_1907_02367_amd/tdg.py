@@ -297,6 +297,13 @@ class Trefftz:
 
         return self.buffers[2][: self.nq * (self.n + 2) * 8].view(torch.float64).view(self.ne, self.n + 2, self.Q)
 
+    def indicator_tensor(self):
+        """Device view (n_tents,) float64 of the per-tent indicator written by
+        solves with the indicator on (trefftz_set_indicator)."""
+        import torch
+
+        return self.buffers[7][: self.tents.n_tents * 8].view(torch.float64)
+
     def set_initial(self, v0, sigma0, U0=None):
         v0 = np.ascontiguousarray(v0, dtype=np.float64).reshape(-1)
         s0 = np.ascontiguousarray(sigma0, dtype=np.float64).reshape(-1)
