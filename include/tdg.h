@@ -212,8 +212,8 @@ int trefftz_layer_indicator(tdg_ctx* ctx, int32_t layer, int32_t p, double* eta,
  * network (w_bf16, tdg_mlp_nparam() BF16 values): per layer, features ->
  * feats, the network's predicted log eta_T(p) for p = 2..8 -> p_sel[tent] =
  * the smallest p <= p_max whose prediction is <= log_eta_tol (else p_max); a
- * tent whose realised eta_T exceeds eta_tol (if > 0) is solved again at p_max
- * before anything is written.  w_bf16 = NULL: fixed p_max everywhere (the
+ * tent whose realised eta_T exceeds eta_tol (if > 0) is solved again one
+ * degree higher, up to p_max (accepted there), before anything is written.  w_bf16 = NULL: fixed p_max everywhere (the
  * fallback; p_sel is filled with p_max).  p_used (nullable) gets the degree
  * each tent was finally solved with, eta (nullable) its eta_T. */
 int trefftz_layer_solve_adaptive(tdg_ctx* ctx, int32_t layer_begin, int32_t layer_end, const uint16_t* w_bf16,

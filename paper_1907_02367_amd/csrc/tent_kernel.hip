@@ -23,7 +23,8 @@
 //   5. optional indicator: energy of the jump between the new solution and the
 //      incoming trace on the bottom facets (a term of the tent's energy
 //      balance); a tent solved below p_max whose indicator exceeds the
-//      tolerance is solved again at p_max before anything is written
+//      tolerance is solved again one degree higher (up to p_max) before
+//      anything is written
 //   6. (v, sigma, U) at the top points overwrite the stored values; tau_V = t_top.
 #include <hip/hip_runtime.h>
 
@@ -302,9 +303,10 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   double* A = L.A_in_lds ? lds + L.off_A : P.work + (long long)blockIdx.x * P.work_stride;
 
   // A tent solved at a degree below p_max whose realised indicator exceeds the
-  // tolerance is solved again at p_max (second pass of this loop).
+  // tolerance is solved again one degree higher (at most up to p_max, where it
+  // is accepted); nothing is written before the accepted attempt.
   for (int dtry = 0;; ++dtry) {
-  const int p = dtry == 0 ? p_in : P.pmax;
+  const int p = min(p_in + dtry, P.pmax);
   // chunk size and operand stride of degree p (lower degrees take larger chunks)
   const int PCH = L.pch[p];
   const int LD2 = 2 * PCH;  // row stride of the monomial table (top points, then bottom points)
@@ -1197,7 +1199,7 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   // ---- 5. indicator: energy of the jump between the solution and the incoming
   //         trace on the bottom facets, 1/2 B_phi_old(u - u_b, u - u_b)
   double* cm = W1;  // (NS+2) x M: coefficients of v, sigma, U on the monomials, contracted with x
-  const bool want_eta = P.indicator || !P.write_back || (P.eta_tol > 0.0 && dtry == 0 && p < P.pmax);
+  const bool want_eta = P.indicator || !P.write_back || (P.eta_tol > 0.0 && p < P.pmax);
   if (want_eta) {
     double eta_loc = 0.0;
     for (int r = 0; r < m; ++r) {
@@ -1266,7 +1268,7 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     __syncthreads();
     double eta = 0.0;
     for (int w = 0; w < (int)blockDim.x / 64; ++w) eta += s_red[w];
-    const bool redo = P.eta_tol > 0.0 && dtry == 0 && p < P.pmax && eta > P.eta_tol;
+    const bool redo = P.eta_tol > 0.0 && p < P.pmax && eta > P.eta_tol;
     __syncthreads();
     if (redo) continue;
     if (tid == 0 && P.dissip) P.dissip[tent] = eta;

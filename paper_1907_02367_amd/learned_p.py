@@ -16,11 +16,12 @@ step are the library's kernels (tdg_mlp_*), the host only slices mini-batches.
 Use.  Per layer the library computes the features, evaluates the network and
 gives each tent the smallest degree whose predicted log indicator is below
 log_eta_tol (else p_max); a tent whose realised indicator exceeds eta_tol is
-solved again at p_max before anything is written, so fixed-p_max is both the
-fallback and the judge.
+solved again one degree higher (up to p_max, where it is accepted) before
+anything is written, so fixed-p_max is both the fallback and the judge.
 """
 from __future__ import annotations
 
+import os
 import time
 
 import numpy as np
@@ -28,6 +29,9 @@ import numpy as np
 from . import tdg
 
 N_FEAT, N_OUT = 8, 7
+# network trained by paper_1907_02367_amd.studies.learned on 3+1D unit-cube
+# meshes (p_max = 8; sizes 3, 5 and the first layers of 25 cells per side)
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "degree_net_3d.npz")
 
 
 def _torch():
@@ -100,6 +104,13 @@ class DegreeNet:
         tdg.mlp_round(self.w32, self.wb)
 
 
+def load_default():
+    """The packaged degree network (FP32 master weights and their BF16 copy)."""
+    net = DegreeNet(seed=0)
+    net.load_state_dict(np.load(DEFAULT_WEIGHTS))
+    return net
+
+
 def make_context(pr, p_max=None, precision=0, device=None):
     """Library context of a workload (synthetic inputs resident on the GPU)."""
     f = pr.data
@@ -122,14 +133,15 @@ def make_context(pr, p_max=None, precision=0, device=None):
     return ctx, xq
 
 
-def collect(ctx, p_list=range(2, 9), layer_stride=1, progress=None):
-    """Sweeps the context at p_max; before every `layer_stride`-th layer,
-    records the features and eta_T(p) for p in p_list of its tents.
-    Returns device tensors X (n x 8), Y = log eta (n x 7), M (n x 7 mask).
-    progress(l, L), if given, is called after every tenth layer."""
+def collect(ctx, p_list=range(2, 9), layer_stride=1, progress=None, max_layers=None):
+    """Sweeps the context at p_max (the first max_layers layers, default all);
+    before every `layer_stride`-th layer, records the features and eta_T(p)
+    for p in p_list of its tents.  Returns device tensors X (n x 8),
+    Y = log eta (n x 7), M (n x 7 mask).  progress(l, L), if given, is called
+    after every tenth layer."""
     torch = _torch()
     nt = ctx.tents.n_tents
-    L = ctx.tents.n_layers
+    L = ctx.tents.n_layers if max_layers is None else min(max_layers, ctx.tents.n_layers)
     lp = ctx.tents.layer_ptr
     feats = torch.zeros((nt, N_FEAT), dtype=torch.float32, device="cuda")
     eta = torch.full((N_OUT, nt), -1.0, dtype=torch.float64, device="cuda")
@@ -160,10 +172,14 @@ def collect(ctx, p_list=range(2, 9), layer_stride=1, progress=None):
     return X, Y, M.float().contiguous()
 
 
-def adaptive_sweep(ctx, net, log_eta_tol, eta_tol, stream=None, buffers=None):
+def adaptive_sweep(ctx, net, log_eta_tol, eta_tol, stream=None, buffers=None, want_eta=False, block=0,
+                   progress=None, layer_end=None):
     """One degree-adaptive sweep of all layers (from the current state).
-    net = None: fixed p_max (the fallback).  Returns the buffers
-    (feats, p_sel, p_used, eta) as device tensors."""
+    net = None: fixed p_max (the fallback).  want_eta: also record eta_T of
+    every tent (costs an evaluation at the bottom points of each tent).
+    block > 0: launch in blocks of that many layers, calling progress(l, L)
+    after each (synchronised).  Returns the buffers (feats, p_sel, p_used, eta)
+    as device tensors."""
     torch = _torch()
     nt = ctx.tents.n_tents
     if buffers is None:
@@ -172,9 +188,46 @@ def adaptive_sweep(ctx, net, log_eta_tol, eta_tol, stream=None, buffers=None):
                    torch.zeros(nt, dtype=torch.int8, device="cuda"),
                    torch.zeros(nt, dtype=torch.float64, device="cuda"))
     feats, p_sel, p_used, eta = buffers
-    ctx.layer_solve_adaptive(None if net is None else net.wb, log_eta_tol, eta_tol, feats, p_sel, p_used, eta,
-                             stream=stream)
+    L = ctx.tents.n_layers if layer_end is None else layer_end
+    step = block if block > 0 else L
+    for l0 in range(0, L, max(step, 1)):
+        l1 = min(L, l0 + step)
+        ctx.layer_solve_adaptive(None if net is None else net.wb, log_eta_tol, eta_tol, feats, p_sel, p_used,
+                                 eta if want_eta else None, layer_begin=l0, layer_end=l1, stream=stream)
+        if progress is not None and block > 0:
+            torch.cuda.synchronize()
+            progress(l1, L)
     return buffers
+
+
+def fixed_sweep(ctx, block=0, progress=None, layer_end=None):
+    """Plain sweep at p_max, optionally in blocks of layers with progress."""
+    torch = _torch()
+    L = ctx.tents.n_layers if layer_end is None else layer_end
+    step = block if block > 0 else L
+    for l0 in range(0, L, max(step, 1)):
+        l1 = min(L, l0 + step)
+        ctx.layer_solve(l0, l1)
+        if progress is not None and block > 0:
+            torch.cuda.synchronize()
+            progress(l1, L)
+
+
+def front_error(ctx, coords, elems, xq, field=None, ref=None):
+    """Error e (the c^-2-weighted L2 norm of Sec. 6) of the stored values on
+    the current front, against the exact field at each point's own time on
+    the front (field) or against reference values at the same points (ref =
+    (v, sigma) of another sweep over the same layers).  Returns (e_abs, e_rel)."""
+    if ref is not None:
+        return ctx.eval_error(ref[0], ref[1])
+    coords = np.asarray(coords, dtype=np.float64)
+    elems = np.asarray(elems)
+    n, Q = ctx.n, ctx.Q
+    # barycentric coordinates of the reference points (the same in every element)
+    B = np.vstack([coords[elems[0]].T, np.ones(n + 1)])
+    lam = np.linalg.solve(B, np.vstack([xq[:Q].T, np.ones(Q)])).T  # Q x (n+1)
+    tq = (ctx.front()[elems] @ lam.T).reshape(-1)  # ne*Q, element-major
+    return ctx.eval_error(field.v(xq, tq), field.sigma(xq, tq))
 
 
 def dof_count(ctx, p_used):

@@ -49,7 +49,7 @@ def train_problems(ms, seeds, p_max, T):
     return [problem(m, p_max, seed, T, v) for m in ms for seed in seeds for v in ("a", "b")]
 
 
-def build_dataset(problems, layer_stride=1):
+def build_dataset(problems, layer_stride=1, max_layers=None):
     import torch
 
     from paper_1907_02367_amd import learned_p as LP
@@ -60,7 +60,8 @@ def build_dataset(problems, layer_stride=1):
         ctx, _ = LP.make_context(pr)
         X, Y, M = LP.collect(ctx, range(2, pr.p + 1), layer_stride,
                              progress=lambda l, L: say(f"[data] {pr.name}: layer {l}/{L} "
-                                                       f"{time.perf_counter() - t0:.1f} s"))
+                                                       f"{time.perf_counter() - t0:.1f} s"),
+                             max_layers=max_layers)
         Xs.append(X)
         Ys.append(Y)
         Ms.append(M)
@@ -70,74 +71,75 @@ def build_dataset(problems, layer_stride=1):
     return torch.cat(Xs).contiguous(), torch.cat(Ys).contiguous(), torch.cat(Ms).contiguous()
 
 
-def evaluate(pr, net, tols, precisions=(0, 1), reps=1):
-    """Fixed p_max FP64 reference, then adaptive sweeps; yields result dicts."""
-    import torch
-
+def evaluate(pr, net, tols, precisions=(0, 1), block=20, window=None):
+    """Fixed p_max FP64 reference, then adaptive sweeps over the first
+    `window` layers (all by default), one timed sweep each, launched in blocks
+    of layers with a progress line per block; yields result dicts.  Errors are
+    taken on the front reached (flat at T for a full sweep), against the
+    exact field at each point's time where there is one, and against the
+    fixed-p_max values."""
     from paper_1907_02367_amd import learned_p as LP
 
     f = pr.data
     ctx, xq = LP.make_context(pr)
-    nt = ctx.tents.n_tents
+    L = ctx.tents.n_layers if window is None else min(window, ctx.tents.n_layers)
+    nt = int(ctx.tents.layer_ptr[L])
     N = {p: ctx.table_info(p)["N"] for p in range(1, pr.p + 1)}
     dof_fixed = nt * N[pr.p]
 
-    def sweep_fixed():
-        ctx.reset()
-        ctx.layer_solve()
+    def prog(tag):
+        t0 = time.perf_counter()
+        return lambda l, LL: say(f"[{tag}] layer {l}/{LL} {time.perf_counter() - t0:.1f} s")
 
-    sweep_fixed()
-    ctx.status()
-    t_fixed = LP.timed(sweep_fixed, reps)
+    def errs(c, ref=None):
+        e_ex = LP.front_error(c, pr.coords, pr.elems, xq, field=f)[0] if pr.exact else None
+        e_ref = LP.front_error(c, pr.coords, pr.elems, xq, ref=ref)[0] if ref is not None else 0.0
+        return e_ex, e_ref
+
+    t_fixed = LP.timed(lambda: LP.fixed_sweep(ctx, block, prog(f"{pr.name} fixed"), layer_end=L))
     ctx.status()
     v_ref, s_ref, _ = ctx.read_state()
-    e_exact_fixed = ctx.eval_error(f.v(xq, pr.T), f.sigma(xq, pr.T)) if pr.exact else (None, None)
-    base = dict(workload=pr.name, ne=len(pr.elems), tents=nt, layers=ctx.tents.n_layers, p_max=pr.p)
+    e_ex, _ = errs(ctx)
+    base = dict(workload=pr.name, ne=len(pr.elems), tents=nt, layers=L, layers_total=ctx.tents.n_layers,
+                p_max=pr.p)
     yield dict(base, run="fixed_pmax_fp64", time_s=t_fixed, dof_updates=dof_fixed,
-               rate_equiv=dof_fixed / t_fixed, e_vs_exact=e_exact_fixed[0], e_vs_fixed=0.0)
+               rate_equiv=dof_fixed / t_fixed, e_vs_exact=e_ex, e_vs_fixed=0.0)
     for prec in precisions:
         c2 = ctx if prec == 0 else LP.make_context(pr, precision=1)[0]
         bufs = None
         for log_tol in tols:
             eta_tol = float(np.exp(log_tol)) * 10.0
+            c2.reset()
+            holder = {}
 
             def sweep():
-                nonlocal bufs
-                c2.reset()
-                bufs = LP.adaptive_sweep(c2, net, log_tol, eta_tol, buffers=bufs)
+                holder["b"] = LP.adaptive_sweep(c2, net, log_tol, eta_tol, buffers=bufs, block=block,
+                                                progress=prog(f"{pr.name} learned {log_tol}"), layer_end=L)
 
-            sweep()
+            t = LP.timed(sweep)
+            bufs = holder["b"]
             c2.status()
-            t = LP.timed(sweep, reps)
-            c2.status()
-            pu = bufs[2].cpu().numpy()
-            ps = bufs[1].cpu().numpy()
+            pu = bufs[2].cpu().numpy()[:nt]
+            ps = bufs[1].cpu().numpy()[:nt]
             dofs = LP.dof_count(c2, pu)
-            e_fixed = c2.eval_error(v_ref, s_ref)[0]
-            e_ex = c2.eval_error(f.v(xq, pr.T), f.sigma(xq, pr.T))[0] if pr.exact else None
+            e_ex, e_fixed = errs(c2, (v_ref, s_ref))
             yield dict(base, run=f"learned_{'fp64' if prec == 0 else 'mixed'}", log_eta_tol=log_tol,
                        eta_tol=eta_tol, time_s=t, dof_updates=dofs, rate_equiv=dof_fixed / t,
                        speedup=t_fixed / t, e_vs_exact=e_ex, e_vs_fixed=e_fixed,
                        p_hist={int(p): int((pu == p).sum()) for p in range(2, pr.p + 1)},
-                       resolved=int(((pu == pr.p) & (ps < pr.p)).sum()))
+                       resolved=int((pu > ps).sum()))
         if prec == 1:
-            # fixed p_max in mixed precision
-            def sweep_m():
-                c2.reset()
-                c2.layer_solve()
-
-            sweep_m()
+            c2.reset()
+            t = LP.timed(lambda: LP.fixed_sweep(c2, block, prog(f"{pr.name} fixed mixed"), layer_end=L))
             c2.status()
-            t = LP.timed(sweep_m, reps)
-            c2.status()
-            e_fixed = c2.eval_error(v_ref, s_ref)[0]
+            e_ex, e_fixed = errs(c2, (v_ref, s_ref))
             yield dict(base, run="fixed_pmax_mixed", time_s=t, dof_updates=dof_fixed, rate_equiv=dof_fixed / t,
-                       speedup=t_fixed / t, e_vs_fixed=e_fixed)
+                       speedup=t_fixed / t, e_vs_exact=e_ex, e_vs_fixed=e_fixed)
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train-m", default="2,3")
+    ap.add_argument("--train-m", default="3,5,7")
     ap.add_argument("--train-seeds", default="1,2")
     ap.add_argument("--train-T", type=float, default=0.3)
     ap.add_argument("--eval-m", default="4")
@@ -147,6 +149,12 @@ def main():
     ap.add_argument("--layer-stride", type=int, default=1)
     ap.add_argument("--tols", default="-30,-34,-38,-42")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--eval-variants", default="b,a")
+    ap.add_argument("--eval-window", type=int, default=0, help="layers per evaluation sweep (0: all)")
+    ap.add_argument("--train-window-m", default="", help="mesh sizes sampled over their first layers only")
+    ap.add_argument("--train-window", type=int, default=16)
+    ap.add_argument("--save-data", default="", help="write the training set (npz)")
+    ap.add_argument("--load-data", default="", help="training sets (npz, comma-separated) to add")
     ap.add_argument("--save", default="")
     ap.add_argument("--load", default="")
     ap.add_argument("--out", default="")
@@ -171,9 +179,21 @@ def main():
     if args.load:
         net.load_state_dict(np.load(args.load))
     else:
-        probs = train_problems([int(x) for x in args.train_m.split(",")], [int(x) for x in args.train_seeds.split(",")],
-                               args.p_max, args.train_T)
-        X, Y, M = build_dataset(probs, args.layer_stride)
+        ints = lambda a: [int(x) for x in a.split(",")] if a else []  # noqa: E731
+        parts = []
+        probs = train_problems(ints(args.train_m), ints(args.train_seeds), args.p_max, args.train_T)
+        if probs:
+            parts.append(build_dataset(probs, args.layer_stride))
+        wprobs = train_problems(ints(args.train_window_m), ints(args.train_seeds), args.p_max, args.eval_T)
+        if wprobs:
+            parts.append(build_dataset(wprobs, args.layer_stride, max_layers=args.train_window))
+        if args.load_data:
+            for path in args.load_data.split(","):
+                d = np.load(path)
+                parts.append(tuple(torch.from_numpy(d[k]).cuda() for k in ("X", "Y", "M")))
+        X, Y, M = (torch.cat([pt[i] for pt in parts]).contiguous() for i in range(3))
+        if args.save_data:
+            np.savez(args.save_data, X=X.cpu().numpy(), Y=Y.cpu().numpy(), M=M.cpu().numpy())
         # output bias at the per-degree mean of the targets
         mean = ((Y * M).sum(0) / M.sum(0).clamp(min=1)).cpu().numpy()
         net.set_output_bias(mean)
@@ -193,11 +213,12 @@ def main():
                   val_rmse_log_eta=rmse, mean_log_eta_by_p=[float(x) for x in mean]))
         if args.save:
             np.savez(args.save, **net.state_dict())
-    tols = [float(x) for x in args.tols.split(",")]
-    for m in [int(x) for x in args.eval_m.split(",")]:
-        for variant in ("b", "a"):
+    tols = [float(x) for x in args.tols.split(",")] if args.tols else []
+    for m in ([int(x) for x in args.eval_m.split(",")] if args.eval_m else []):
+        for variant in args.eval_variants.split(","):
             pr = problem(m, args.p_max, 7, args.eval_T, variant)
-            for d in evaluate(pr, net, tols, precisions=(0,) if args.no_mixed else (0, 1)):
+            for d in evaluate(pr, net, tols, precisions=(0,) if args.no_mixed else (0, 1),
+                              window=args.eval_window or None):
                 emit(d)
 
 

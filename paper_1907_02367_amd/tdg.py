@@ -247,6 +247,7 @@ class Trefftz:
     def __init__(self, coords, elems, c, tents: Tents, p_max: int, q: int = 0, alpha: float = 0.5,
                  beta: float = 0.5, precision: int = 0, recover_U: int = 1, device=None, bind: bool = True):
         self.n = int(np.asarray(coords).shape[1])
+        self.nv = int(np.asarray(coords).shape[0])
         self.ne = int(np.asarray(elems).shape[0])
         self.tents = tents
         m, keep = _mesh(coords, elems)
@@ -296,6 +297,13 @@ class Trefftz:
         import torch
 
         return self.buffers[2][: self.nq * (self.n + 2) * 8].view(torch.float64).view(self.ne, self.n + 2, self.Q)
+
+    def front(self):
+        """Host copy of the advancing front (one time per vertex)."""
+        import torch
+
+        torch.cuda.synchronize()
+        return self.buffers[4][: self.nv * 8].view(torch.float64).cpu().numpy()
 
     def indicator_tensor(self):
         """Device view (n_tents,) float64 of the per-tent indicator written by

@@ -172,9 +172,9 @@ def test_features_and_indicator_match_oracle(name):
 
 def test_adaptive_sweep_matches_oracle_with_same_degrees():
     """A network that reads the patch size gives a spread of degrees; the
-    library records the degree each tent was solved with (after any re-solve
-    at p_max), and the oracle run with exactly those degrees must agree to the
-    FP64 bar."""
+    library records the degree each tent was solved with (after any re-solves
+    at higher degrees), and the oracle run with exactly those degrees must
+    agree to the FP64 bar."""
     torch = _torch()
     pr = C.cfg2_plane_2d(m=8, p=5)
     o = oracle_for(pr)
@@ -208,10 +208,11 @@ def test_adaptive_sweep_matches_oracle_with_same_degrees():
     so = OM.select_degree(yo, log_tol, pr.p)
     near = np.any(np.abs(yo[:, : pr.p - 1] - log_tol) < 1e-4, axis=1)
     assert np.array_equal(ps[~near], so[~near])
-    # re-solve rule
-    assert np.all((pu == ps) | (pu == pr.p))
+    # re-solve rule: degrees only go up, and a tent below p_max was accepted
+    # only with its realised indicator within the tolerance
+    assert np.all(pu >= ps)
     assert np.all(et[pu < pr.p] <= eta_tol)
-    assert np.all(et[(pu == pr.p) & (ps < pr.p)] >= 0)
+    assert np.all(et >= 0)
     o.run(p_per_tent=pu)
     v, s, U = ctx.read_state()
     r_vs = rel_l2(np.concatenate([v.ravel(), s.ravel()]), np.concatenate([o.v.ravel(), o.sig.ravel()]))
@@ -250,3 +251,52 @@ def test_indicator_rejects_bad_degree():
         ctx.layer_indicator(ctx.tents.n_layers, 2, eta)
     with pytest.raises(ValueError):
         ctx.layer_indicator(0, 2, eta[:-1])
+
+
+def test_trained_network_gains_over_fixed_pmax():
+    """What the packaged network buys on a 3+1D mesh (18 cells per side, 34,992
+    tetrahedra, p_max = 8, exact standing wave; layers are wider than the
+    GPU has compute units): over the first 12 layers, the degree-adaptive sweep
+    does fewer DOF-updates and takes less time than fixed p = 8, with the
+    error against the exact solution on the reached front and against the
+    fixed-p solution both below 1e-6."""
+    import time
+
+    torch = _torch()
+    from paper_1907_02367_amd import learned_p as LP
+    from workloads import configs as Cf
+
+    pr = Cf.cfg5_cube_3d(m=18, p=8, seed=7, T=0.5, variant="b", regions=1)
+    net = LP.load_default()
+    ctx, xq = LP.make_context(pr)
+    W = 12
+    nt = int(ctx.tents.layer_ptr[W])
+    say(f"[learned gain] m=18: {nt} tents in the first {W} layers")
+
+    def run(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    t_fixed = run(lambda: ctx.layer_solve(0, W))
+    ctx.status()
+    v_ref, s_ref, _ = ctx.read_state()
+    e_fixed = LP.front_error(ctx, pr.coords, pr.elems, xq, field=pr.data)[0]
+    ctx.reset()
+    holder = {}
+    t_learned = run(lambda: holder.update(b=LP.adaptive_sweep(ctx, net, -43.0, 10 * np.exp(-43.0), layer_end=W)))
+    ctx.status()
+    pu = holder["b"][2].cpu().numpy()[:nt]
+    ps = holder["b"][1].cpu().numpy()[:nt]
+    e_learned = LP.front_error(ctx, pr.coords, pr.elems, xq, field=pr.data)[0]
+    e_vs_fixed = LP.front_error(ctx, pr.coords, pr.elems, xq, ref=(v_ref, s_ref))[0]
+    dof_fixed = nt * ctx.table_info(8)["N"]
+    dof_learned = LP.dof_count(ctx, pu)
+    say(f"  fixed p=8: {t_fixed:.2f} s, e {e_fixed:.2e}; learned: {t_learned:.2f} s, e {e_learned:.2e} "
+        f"(vs fixed {e_vs_fixed:.2e}), DOF-updates {dof_learned / dof_fixed:.3f} of fixed, degrees "
+        f"{np.bincount(pu, minlength=9)[2:]}, re-solved higher {int((pu > ps).sum())}")
+    assert e_fixed <= 1e-6 and e_learned <= 1e-6 and e_vs_fixed <= 1e-6
+    assert dof_learned <= 0.9 * dof_fixed
+    assert t_learned < 0.9 * t_fixed
