@@ -69,6 +69,73 @@ def op_counts(ctx, pr, tents):
     return flops, bytes_, info["N"]
 
 
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("tent_kernel.hip", "tdg_internal.h"):
+        with open(os.path.join(ROOT, "paper_1907_02367_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per tent-kernel launch from the committed rocprofv3 counter
+    summary of this workload, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"tent_layer_kernel_{workload_name}_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return float(d["hbm_bytes_per_launch"])
+
+
+def learned_3d(m=18, window=12, log_tol=-43.0):
+    """Degree-adaptive (packaged network) vs fixed p = 8 on a 3+1D unit cube
+    (m cells per side, 6 m^3 tetrahedra, c = 1.5, exact standing wave), over the
+    first `window` layers, in FP64 and with the mixed-precision local solve.
+    Errors: the paper's e on the reached front against the exact field at
+    each point's time."""
+    import torch
+
+    from paper_1907_02367_amd import learned_p as LP
+    from workloads import configs as C
+
+    pr = C.cfg5_cube_3d(m=m, p=8, seed=7, T=0.5, variant="b", regions=1)
+    net = LP.load_default()
+    out = {"workload": f"3+1D unit cube, {m}^3 x 6 jittered Kuhn tets ({len(pr.elems)}), c=1.5, standing wave, "
+                       f"p_max=8, first {window} layers",
+           "log_eta_tol": log_tol}
+    for prec in (0, 1):
+        ctx, xq = LP.make_context(pr, precision=prec)
+        nt = int(ctx.tents.layer_ptr[window])
+        dof_fixed = nt * ctx.table_info(8)["N"]
+        tag = "fp64" if prec == 0 else "mixed"
+        if prec == 0:
+            t = LP.timed(lambda: ctx.layer_solve(0, window))
+            ctx.status()
+            e = LP.front_error(ctx, pr.coords, pr.elems, xq, field=pr.data)[0]
+            out["tents"] = nt
+            out["fixed_fp64"] = {"time_s": t, "dof_updates_per_s": dof_fixed / t, "e": e}
+            ctx.reset()
+        holder = {}
+        t = LP.timed(lambda: holder.update(b=LP.adaptive_sweep(ctx, net, log_tol, 10 * np.exp(log_tol),
+                                                               layer_end=window)))
+        ctx.status()
+        pu = holder["b"][2].cpu().numpy()[:nt]
+        e = LP.front_error(ctx, pr.coords, pr.elems, xq, field=pr.data)[0]
+        out[f"learned_{tag}"] = {"time_s": t, "equiv_dof_updates_per_s": dof_fixed / t,
+                                 "dof_updates_done": LP.dof_count(ctx, pu), "e": e,
+                                 "speedup_vs_fixed_fp64": out["fixed_fp64"]["time_s"] / t,
+                                 "degrees": {int(p): int((pu == p).sum()) for p in range(2, 9) if (pu == p).any()}}
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(pr, budget_s: float):
     from oracle.pitcher import pitch
     from oracle.tdg import OracleTDG
@@ -102,6 +169,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (automatic shape)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the 3+1D learned-degree comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
@@ -144,6 +212,13 @@ def main():
             if events is not None:
                 events[l][1].record(stream)
 
+    # a plain device copy of known size (256 MiB), outside the timed region: the
+    # reference for scaling hardware byte counters in profiles of this command
+    calib = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    calib2 = torch.empty_like(calib)
+    calib2.copy_(calib)
+    torch.cuda.synchronize()
+    del calib, calib2
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -200,12 +275,14 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK, "traffic": None,
+            "frac": achieved / FP64_PEAK, "traffic": measured_traffic(args.workload),
             "kernel": f"tent_layer_kernel<{pr.n}>", "launches_per_step": int(L),
             "avg_launch_us": avg_launch_s * 1e6, "alg_flops_per_launch": float(flops_per_launch),
             "alg_bytes_per_launch": float(bytes_.sum() / L),
         },
     }
+    if not args.no_learned:
+        out["learned_3d"] = learned_3d()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)
