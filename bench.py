@@ -44,6 +44,11 @@ def workload(name):
     elif name == "cfg1":
         pr = C.cfg1_standing_1d()
         desc = "1+1D plain: [0,1], 16 elements, c=1, p=3, standing wave, T=1"
+    elif name == "cfg4":
+        pr = C.cfg4_interface_2d()
+        desc = ("2+1D heterogeneous uneven batch: unit square, mesh aligned with x=0.5 "
+                f"({len(pr.elems)} triangles), c=1 (x<0.5) / 3 (x>0.5), p=4 (25 per speed group, 50 on "
+                "interface tents), Gaussian pulse width 0.05 at a seeded centre, homogeneous Dirichlet, T=1")
     elif name.startswith("cfg3"):
         p = int(name.split("p")[-1]) if "p" in name else 8
         pr = C.cfg3_precision_2d(p=p)
@@ -54,19 +59,28 @@ def workload(name):
 
 
 def op_counts(ctx, pr, tents):
-    """Algorithmic flops and HBM bytes per tent (point-value layout):
+    """Algorithmic flops, HBM bytes and unknowns per tent (point-value layout):
     flops = 2*(2 Q_T nnz) [fields at top and bottom points] + K NW (NW+1) [symmetric Gram]
-          + 4 K NW [right-hand side and top evaluation] + 2/3 NW^3 + 2 NW^2 [LU and solve],
-    K = Q_T (n+1), Q_T = patch size * points per element; bytes = 2 Q_T (n+2) 8."""
+          + 4 K NW [right-hand side and top evaluation] + 2/3 S^3 + 2 S^2 [LU and solve],
+    K = Q_T (n+1), Q_T = patch size * points per element, S = groups * NW (one
+    Trefftz space per speed group); face terms are not counted.
+    bytes = 2 Q_T (n+2) 8; unknowns (DOFs) = groups * N."""
     info = ctx.table_info(pr.p)
     NW = info["N"] - 1
     n = pr.n
-    patch = np.bincount(pr.elems.ravel(), minlength=len(pr.coords))
+    nv = len(pr.coords)
+    patch = np.bincount(pr.elems.ravel(), minlength=nv)
+    # speed groups per vertex: distinct speeds among the patch elements
+    _, cid = np.unique(pr.c, return_inverse=True)
+    pairs = np.unique(np.stack([pr.elems.ravel(), np.repeat(cid, n + 1)], axis=1), axis=0)
+    groups = np.bincount(pairs[:, 0], minlength=nv)
     QT = patch[tents.vertex].astype(np.float64) * info["Q"]
+    m = groups[tents.vertex].astype(np.float64)
     K = QT * (n + 1)
-    flops = 4.0 * QT * info["nnz_fields"] + K * NW * (NW + 1) + 4.0 * K * NW + (2.0 / 3.0) * NW ** 3 + 2.0 * NW ** 2
+    S = m * NW
+    flops = 4.0 * QT * info["nnz_fields"] + K * NW * (NW + 1) + 4.0 * K * NW + (2.0 / 3.0) * S ** 3 + 2.0 * S ** 2
     bytes_ = 2.0 * QT * (n + 2) * 8
-    return flops, bytes_, info["N"]
+    return flops, bytes_, m * info["N"]
 
 
 def kernel_source_hash():
@@ -136,13 +150,17 @@ def learned_3d(m=18, window=12, log_tol=-43.0):
     return out
 
 
-def cpu_baseline(pr, budget_s: float):
+def cpu_baseline(pr, budget_s: float, dofs_per_tent, n_tents_gpu):
+    """The oracle on the first layers of the same workload.  For large
+    workloads the oracle pitches only up to a shorter final time (the first
+    layers are the same tents; the pure-Python pitcher would otherwise take
+    longer than the whole budget)."""
     from oracle.pitcher import pitch
     from oracle.tdg import OracleTDG
-    from oracle.trefftz import dim_U
 
     f = pr.data
-    tents, lp = pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    T_or = pr.T * min(1.0, 60000.0 / max(n_tents_gpu, 1))
+    tents, lp = pitch(pr.coords, pr.elems, pr.c, T_or, pr.gamma)
     o = OracleTDG(pr.coords, pr.elems, pr.c, tents, lp, p=pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta,
                   gD=lambda x, t: f.v(x, t))
     X = o.quad_points()
@@ -154,10 +172,21 @@ def cpu_baseline(pr, budget_s: float):
         layers += 1
     el = time.perf_counter() - t0
     ntents = lp[layers]
-    dofs = ntents * dim_U(pr.n, pr.p)
+    # unknowns per tent of the oracle's own tents (speed groups x dim U^p)
+    dofs = float(np.sum(dofs_per_tent[:ntents])) if T_or == pr.T else None
+    if dofs is None:
+        from oracle.trefftz import dim_U
+
+        groups = [len({pr.c[e] for e in o.topo.patch[V]}) for V, _, _ in tents[:ntents]]
+        dofs = float(sum(groups)) * dim_U(pr.n, pr.p)
     return {"value": dofs / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {layers} of {len(lp) - 1} layers ({ntents} tents) in {el:.1f} s, one Python/NumPy "
                       f"process (FP64, LAPACK LU)"}
+
+
+def say(msg):
+    """Progress of the run (stderr; the JSON line is the only stdout output)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -170,10 +199,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (automatic shape)")
     ap.add_argument("--no-learned", action="store_true", help="skip the 3+1D learned-degree comparison")
+    ap.add_argument("--gram", type=int, default=-1, choices=(-1, 0, 1),
+                    help="Gram mode: 0 basis values on the matrix cores, 1 monomial moments, -1 autotuned")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
-              "DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); domain-decomposed runs over several "
+              "GPUs are not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -183,19 +214,25 @@ def main():
     torch.cuda.set_device(0)
     pr, desc = workload(args.workload)
     f = pr.data
+    say(f"workload {args.workload}: {len(pr.elems)} elements")
     tents = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    say(f"pitched: {tents.n_tents} tents in {tents.n_layers} layers")
     ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, tents, p_max=pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta)
     xq, _ = ctx.quad_points()
     ctx.set_initial(f.v(xq, 0.0), f.sigma(xq, 0.0), f.U(xq, 0.0))
     if ctx.nb:
         bx = ctx.boundary_points()
         ctx.set_boundary(f.v(bx[:, :-1], bx[:, -1]))
-    tuned = None
+    say("context bound, initial and boundary data uploaded")
+    tuned, tune_ms = None, {}
     if not args.no_tune:
         from paper_1907_02367_amd.autotune import autotune
 
-        tuned, _ = autotune(ctx, use_cache=False)
+        tuned, tune_ms = autotune(ctx, use_cache=False, modes=None if args.gram < 0 else (args.gram,))
+    elif args.gram > 0:
+        ctx.set_gram_mode(args.gram)
     shape = ctx.get_tuning()
+    shape["gram_mode"] = ctx.get_gram_mode()
     flops, bytes_, N = op_counts(ctx, pr, tents)
     L = tents.n_layers
     lp = tents.layer_ptr
@@ -219,9 +256,11 @@ def main():
     calib2.copy_(calib)
     torch.cuda.synchronize()
     del calib, calib2
+    say(f"shape {ctx.get_tuning()}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    say("warm-up done")
     ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(L)]
           for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -229,6 +268,7 @@ def main():
     for s in range(args.steps):
         step(ev[s])
     torch.cuda.synchronize()
+    say(f"{args.steps} timed steps done")
     wall = time.perf_counter() - t0
     ctx.status()
     ms_per_step = 1e3 * wall / args.steps
@@ -236,7 +276,11 @@ def main():
     avg_launch_s = kern_ms.mean() * 1e-3
     flops_per_launch = layer_flops.mean()
     achieved = flops_per_launch / avg_launch_s
-    e_abs, e_rel = ctx.eval_error(f.v(xq, pr.T), f.sigma(xq, pr.T))
+    if pr.exact:
+        e_abs, e_rel = ctx.eval_error(f.v(xq, pr.T), f.sigma(xq, pr.T))
+    else:  # no closed-form solution: report the energy on the final front instead
+        e_abs = e_rel = None
+    E_T, _ = ctx.energy()
     # the same sweep recorded once as a HIP graph and replayed (informational)
     gstream = torch.cuda.Stream()
     with torch.cuda.stream(gstream):
@@ -250,7 +294,7 @@ def main():
         torch.cuda.synchronize()
         graph_ms = 1e3 * (time.perf_counter() - g0) / args.steps
     ctx.status()
-    dofs = float(tents.n_tents * N)
+    dofs = float(N.sum())
     out = {
         "metric": METRIC,
         "value": dofs / (wall / args.steps),
@@ -266,11 +310,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": desc,
-            "tents": int(tents.n_tents), "layers": int(L), "dofs_per_tent": int(N),
-            "dof_updates_per_step": dofs, "e_abs_at_T": e_abs, "e_rel_at_T": e_rel,
+            "tents": int(tents.n_tents), "layers": int(L), "dofs_per_tent_mean": float(N.mean()),
+            "dof_updates_per_step": dofs, "e_abs_at_T": e_abs, "e_rel_at_T": e_rel, "energy_at_T": E_T,
             "kernel_ms_per_step": float(kern_ms.sum(axis=1).mean()),
             "graph_replay_ms_per_step": graph_ms,
             "kernel_shape": shape, "autotuned": tuned is not None,
+            "autotune_ms_first_layers": tune_ms,
             "parallelism": "single GPU, all tents of a layer in one launch",
         },
         "roofline": {
@@ -282,9 +327,11 @@ def main():
         },
     }
     if not args.no_learned:
+        say("learned-degree comparison (3+1D)")
         out["learned_3d"] = learned_3d()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
+        say("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds, N, tents.n_tents)
     print(json.dumps(out), flush=True)
 
 

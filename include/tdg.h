@@ -167,6 +167,17 @@ int trefftz_table_info(const tdg_ctx* ctx, int32_t p, int32_t* N, int32_t* nnz_f
  * uneven size and degree), 0: one workgroup per tent.  Results do not depend
  * on the shape.  TDG_EINVAL if the shape does not fit. */
 int trefftz_set_tuning(tdg_ctx* ctx, int32_t pts_per_chunk, int32_t persistent);
+/* How the top Gram, the bottom right-hand side, the recovery row and the
+ * Dirichlet terms of eq. 4.1 are formed (FP64 contexts):
+ *   mode 0 (default): the fields of the basis at every quadrature point, Gram
+ *     on the matrix cores (work ~ points x N^2);
+ *   mode 1: moments of the monomials of degree <= 2p-2 over the points, then
+ *     the sparse field tables (work ~ points x (monomials of degree <= 2p-2)
+ *     + the table terms), far less at high degree.
+ * Both give the same system up to rounding.  TDG_EINVAL for mode 1 in a
+ * mixed-precision context or if it does not fit in LDS. */
+int trefftz_set_gram_mode(tdg_ctx* ctx, int32_t mode);
+int trefftz_get_gram_mode(const tdg_ctx* ctx, int32_t* mode);
 int trefftz_get_tuning(const tdg_ctx* ctx, int32_t* pts_per_chunk, int32_t* persistent, int32_t* lds_bytes);
 /* Records layers [layer_begin, layer_end) (as trefftz_layer_solve, preceded by
  * trefftz_reset if with_reset) into a HIP graph owned by the context, captured

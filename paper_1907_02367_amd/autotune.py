@@ -1,15 +1,18 @@
 """Autotuner for the execution shape of the tent kernel.
 
-The shape is (points per chunk, persistent grid or one workgroup per tent);
-it changes speed, not results.  Each feasible shape is timed with HIP events
-on the first layers of the sweep (from the initial state), the fastest is
-kept, and the choice is cached in a JSON file keyed by the problem class
-(dimension, degree, speed groups, mesh size, tents per layer).
+The shape is (Gram mode, points per chunk, persistent grid or one workgroup
+per tent); it changes speed, not results beyond rounding.  Each feasible shape
+is timed with HIP events on the first layers of the sweep (from the initial
+state), the fastest is kept, and the choice is cached in a JSON file keyed by
+the problem class (dimension, degree, speed groups, mesh size, tents per
+layer).  Gram modes: 0 = basis values at the points on the matrix cores,
+1 = monomial moments (FP64 contexts only).
 """
 from __future__ import annotations
 
 import json
 import os
+import sys
 
 import numpy as np
 
@@ -20,7 +23,7 @@ SHAPES = [(pch, pers) for pch in (64, 32, 16, 8, 4) for pers in (0, 1)]
 def problem_key(ctx, p_max):
     t = ctx.tents
     width = int(np.diff(t.layer_ptr).mean()) if t.n_layers else 0
-    return f"n{ctx.n}_p{p_max}_ne{ctx.ne}_Q{ctx.Q}_w{width}"
+    return f"n{ctx.n}_p{p_max}_ne{ctx.ne}_Q{ctx.Q}_w{width}_prec{ctx.precision}"
 
 
 def _load():
@@ -40,7 +43,7 @@ def _save(cache):
         pass
 
 
-def autotune(ctx, n_layers=24, reps=2, use_cache=True, p_per_tent=None, verbose=False):
+def autotune(ctx, n_layers=24, reps=2, use_cache=True, p_per_tent=None, verbose=False, modes=None):
     """Picks the fastest feasible shape for ctx and applies it.  Leaves the
     context reset to its initial state.  Returns (shape dict, timings)."""
     import torch
@@ -50,6 +53,7 @@ def autotune(ctx, n_layers=24, reps=2, use_cache=True, p_per_tent=None, verbose=
     if key in cache:
         sh = cache[key]
         try:
+            ctx.set_gram_mode(sh.get("gram_mode", 0))
             ctx.set_tuning(sh["pts_per_chunk"], sh["persistent"])
             ctx.reset()
             return dict(sh, cached=True), {}
@@ -57,8 +61,11 @@ def autotune(ctx, n_layers=24, reps=2, use_cache=True, p_per_tent=None, verbose=
             pass
     L = min(n_layers, ctx.tents.n_layers)
     timings = {}
-    for pch, pers in SHAPES:
+    shapes = [(mode, pch, pers) for mode in (modes if modes is not None else (0, 1)) for pch, pers in SHAPES]
+    for mode, pch, pers in shapes:
         try:
+            ctx.set_tuning(0, 0)
+            ctx.set_gram_mode(mode)
             ctx.set_tuning(pch, pers)
         except Exception:
             continue
@@ -72,17 +79,20 @@ def autotune(ctx, n_layers=24, reps=2, use_cache=True, p_per_tent=None, verbose=
             e1.record()
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1))
-        timings[(pch, pers)] = best
+        timings[(mode, pch, pers)] = best
         if verbose:
-            print(f"  shape pts_per_chunk={pch} persistent={pers}: {best:.3f} ms for {L} layers", flush=True)
+            print(f"  shape gram={mode} pts_per_chunk={pch} persistent={pers}: {best:.3f} ms for {L} layers",
+                  file=sys.stderr, flush=True)
     if not timings:
         raise RuntimeError("no feasible kernel shape")
-    (pch, pers), ms = min(timings.items(), key=lambda kv: kv[1])
+    (mode, pch, pers), ms = min(timings.items(), key=lambda kv: kv[1])
+    ctx.set_tuning(0, 0)
+    ctx.set_gram_mode(mode)
     ctx.set_tuning(pch, pers)
     ctx.reset()
     torch.cuda.synchronize()
-    sh = dict(pts_per_chunk=pch, persistent=pers, ms=ms, layers=L)
+    sh = dict(gram_mode=mode, pts_per_chunk=pch, persistent=pers, ms=ms, layers=L)
     cache[key] = sh
     if use_cache:
         _save(cache)
-    return dict(sh, cached=False), {f"{k[0]}/{k[1]}": v for k, v in timings.items()}
+    return dict(sh, cached=False), {f"{k[0]}/{k[1]}/{k[2]}": v for k, v in timings.items()}

@@ -58,12 +58,16 @@ struct tdg_ctx {
   std::vector<double> hf64;
   std::vector<int> hi32;
   struct TabOff {
-    size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx, ue_ptr, ue_idx, tr_ptr, tr_j;  // i32
+    size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx, ue_ptr, ue_idx, tr_ptr, tr_j, expo2, K2;  // i32
     size_t ue_coef, tr_coef;                                                           // f64
     size_t fo_coef, u_coef, fo_coef32;                 // f64 (fo_coef32: floats packed two per double)
   } toff[kMaxP + 1];
   size_t o_coords, o_c, o_grad, o_det, o_lam, o_w, o_tb, o_tt, o_bpt;         // f64
   size_t o_elems, o_v2e_ptr, o_v2e, o_vb_ptr, o_vb, o_vi_ptr, o_vi, o_tentV;  // i32
+  TableDesc tabd[kMaxP + 1]{};  // per-degree tables and plan, mirrored on the device
+  size_t o_tabd = 0;             // offset (doubles) of the device copy in the FP64 buffer
+  int gram_mode = 0;   // 0: Gram of the basis values at the points (matrix cores); 1: from moments
+  int forced_pch = 0;  // points per chunk set by trefftz_set_tuning (0: largest that fits)
   int64_t sizes[TDG_NBUF]{};
   void* dev[TDG_NBUF]{};
   bool bound = false;
@@ -131,6 +135,58 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
   };
   const Choice order[4] = {{true, true, 16}, {true, false, 16}, {false, true, 4}, {false, false, 4}};
   const int pmax = X->opts.p_max;
+  for (int p = 0; p <= kMaxP; ++p) L.nwp[p] = p >= 1 && p <= pmax ? ((X->tabs[p].NW + 15) / 16) * 16 + 1 : 0;
+  L.moment = (X->gram_mode == 1 && X->opts.precision == 0) ? 1 : 0;
+  if (L.moment) {
+    // moment mode: W1 holds the moments and the bottom data moments (the Z row of
+    // the Gram reuses the latter), later the write-back coefficients with the
+    // monomial table, or the interface face values
+    auto r4 = [](long long v) { return (v + 3) & ~3LL; };
+    long long mom = 0;
+    for (int p = 1; p <= pmax; ++p) {
+      const Table& tb = X->tabs[p];
+      mom = std::max(mom, (long long)(n + 1) * tb.M2 + (long long)(n + 1) * tb.M1 + tb.M);
+    }
+    L.mt_w1 = (int)r4((long long)(n + 2) * Tm.M);
+    for (const Choice& ch : order) {
+      for (int pch : {64, 32, 16, 8, 4}) {
+        if (forced_pch ? pch != forced_pch : pch < ch.min_pch) continue;
+        L.PCH = pch;
+        L.A_in_lds = ch.a;
+        L.tab_in_lds = ch.t;
+        const long long w1 = std::max(mom, (long long)L.mt_w1 + (long long)Tm.M * 2 * pch);
+        long long pw_sz = 0;
+        for (int p = 1; p <= pmax; ++p) {
+          L.pch[p] = pch;
+          int c = pch;
+          while (c > 1 && 4LL * c * L.nwp[p] + (long long)X->tabs[p].M1 * c > w1) c /= 2;
+          L.pci[p] = c;
+          pw_sz = std::max(pw_sz, std::max((long long)pch * (n + 1) * (3 * p), 2LL * pch * (n + 1) * (p + 1)));
+        }
+        int off = 0;
+        auto take = [&](long long cnt) {
+          int o = off;
+          off += (int)((cnt + 3) & ~3LL);
+          return o;
+        };
+        L.off_x = take(L.S + kMaxGroups);
+        L.off_el = take((long long)maxpatch * L.ELS);
+        L.off_misc = take(5 * kMaxGroups + 24 + (long long)kMaxGroups * L.NWP);
+        L.off_pt = take((long long)pch * (2 * (n + 1) + 1 + (n + 2) + n + 1));
+        L.off_pow = take(pw_sz);
+        L.off_mono = 0;
+        L.off_W1 = take(w1);
+        L.off_fg = take((long long)std::max(L.maxfaces, 1) * (2 + n + (n + 1) * (n + 1)));
+        L.off_tab = ch.t ? take(tab_dbl) : 0;
+        L.off_A = ch.a ? take((long long)L.S * L.lda) : 0;
+        L.off_AF = 0;
+        L.off_vec = 0;
+        L.total = off;
+        if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) return TDG_OK;
+      }
+    }
+    return fail(TDG_EINVAL, "tent kernel working set (moment mode) does not fit in LDS");
+  }
   // per-point sizes (doubles) of the chunk regions at degree p with operand stride nwp
   auto pow_sz = [&](int p, long long c) { return 2LL * c * (n + 1) * (p + 1); };
   auto mono_sz = [&](int p, long long c) { return (long long)X->tabs[p].M * 2 * c; };
@@ -139,11 +195,7 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
     return std::max<long long>(c * (n + 3) * nwp, (long long)(n + 2) * X->tabs[p].M);
   };
   const long long pt_per = 2 * (n + 1) + 1 + (n + 2) + n + 1;
-  for (int p = 0; p <= kMaxP; ++p) {
-    L.pch[p] = 0;
-    L.nwp[p] = 0;
-  }
-  for (int p = 1; p <= pmax; ++p) L.nwp[p] = ((X->tabs[p].NW + 15) / 16) * 16 + 1;
+  for (int p = 0; p <= kMaxP; ++p) L.pch[p] = 0;
   for (const Choice& ch : order) {
     for (int pch : {64, 32, 16, 8, 4}) {
       if (forced_pch ? pch != forced_pch : pch < ch.min_pch) continue;
@@ -164,6 +216,7 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         L.pch[p] = c;
       }
       for (;;) {
+        for (int p = 1; p <= pmax; ++p) L.pci[p] = L.pch[p];
         long long pt_sz = 0, pw_sz = 0;
         for (int p = 1; p <= pmax; ++p) {
           pt_sz = std::max(pt_sz, L.pch[p] * pt_per);
@@ -200,6 +253,22 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
     }
   }
   return fail(TDG_EINVAL, "tent kernel working set does not fit in LDS");
+}
+
+// Copies the per-degree descriptors (tables and the current plan) to the device.
+int upload_tabd(tdg_ctx* X, hipStream_t stream, bool async) {
+  for (int p = 1; p <= X->opts.p_max; ++p) {
+    X->tabd[p].pch = X->lp.pch[p];
+    X->tabd[p].nwp = X->lp.nwp[p];
+    X->tabd[p].pci = X->lp.pci[p];
+  }
+  void* dst = (double*)X->dev[TDG_BUF_F64] + X->o_tabd;
+  const size_t bytes = sizeof(TableDesc) * (kMaxP + 1);
+  if (async) {
+    if (hipMemcpyAsync(dst, X->tabd, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return -1;
+    return hipStreamSynchronize(stream) == hipSuccess ? 0 : -1;
+  }
+  return hipMemcpy(dst, X->tabd, bytes, hipMemcpyHostToDevice) == hipSuccess ? 0 : -1;
 }
 
 }  // namespace
@@ -357,6 +426,8 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     o.ue_idx = push(X->hi32, tb.ue_idx.data(), tb.ue_idx.size());
     o.tr_ptr = push(X->hi32, tb.tr_ptr.data(), tb.tr_ptr.size());
     o.tr_j = push(X->hi32, tb.tr_j.data(), tb.tr_j.size());
+    o.expo2 = push(X->hi32, tb.expo2.data(), tb.expo2.size());
+    o.K2 = push(X->hi32, tb.K2.data(), tb.K2.size());
     o.ue_coef = push(X->hf64, tb.ue_coef.data(), tb.ue_coef.size());
     o.tr_coef = push(X->hf64, tb.tr_coef.data(), tb.tr_coef.size());
     o.fo_coef = push(X->hf64, tb.fo_coef.data(), tb.fo_coef.size());
@@ -367,8 +438,23 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     std::memcpy(packed.data(), f32.data(), f32.size() * sizeof(float));
     o.fo_coef32 = push(X->hf64, packed.data(), packed.size());
   }
+  {
+    const size_t nd = (sizeof(TableDesc) * (kMaxP + 1) + 7) / 8;
+    std::vector<double> zeros(nd, 0.0);
+    X->o_tabd = push(X->hf64, zeros.data(), zeros.size());
+  }
   rc = plan_lds(X);
   if (rc) return rc;
+  // global system slots are needed if the systems do not fit in LDS in either
+  // Gram mode (the mode can be switched after binding)
+  bool need_slots = !X->lp.A_in_lds;
+  if (X->opts.precision == 0) {
+    const LdsPlan keep = X->lp;
+    X->gram_mode = 1;
+    if (plan_lds(X) == TDG_OK && !X->lp.A_in_lds) need_slots = true;
+    X->gram_mode = 0;
+    X->lp = keep;
+  }
   // buffer sizes
   const int64_t nst = X->nq * (n + 2);
   X->sizes[TDG_BUF_F64] = (int64_t)X->hf64.size() * 8;
@@ -387,7 +473,7 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     int64_t widest = 0;
     for (size_t l = 0; l + 1 < X->tents.layer_ptr.size(); ++l)
       widest = std::max<int64_t>(widest, X->tents.layer_ptr[l + 1] - X->tents.layer_ptr[l]);
-    X->sys_stride = X->lp.A_in_lds ? 0 : ((int64_t)X->lp.S * X->lp.lda * (X->opts.precision == 1 ? 2 : 1) + 31) / 32 * 32;
+    X->sys_stride = need_slots ? ((int64_t)X->lp.S * X->lp.lda * (X->opts.precision == 1 ? 2 : 1) + 31) / 32 * 32 : 0;
     X->sizes[TDG_BUF_WORK] = (int64_t)(X->w_sys + X->sys_stride * widest) * 8;
   }
   X->sizes[TDG_BUF_TENT] = std::max<int64_t>((int64_t)X->tents.V.size(), 1) * 16;
@@ -487,15 +573,18 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
   P.write_back = 1;
   P.eta_tol = 0.0;
   P.p_used = nullptr;
-  for (int p = 0; p <= kMaxP; ++p) P.tab[p] = TableDesc{};
+  for (int p = 0; p <= kMaxP; ++p) X->tabd[p] = TableDesc{};
   for (int p = 1; p <= X->opts.p_max; ++p) {
     const Table& tb = X->tabs[p];
     const auto& o = X->toff[p];
-    TableDesc& D = P.tab[p];
+    TableDesc& D = X->tabd[p];
     D.p = p;
     D.NW = tb.NW;
     D.M = tb.M;
     D.M1 = tb.M1;
+    D.M2 = tb.M2;
+    D.expo2 = I + o.expo2;
+    D.K2 = I + o.K2;
     D.fo_nnz = (int)tb.fo_idx.size();
     D.u_nnz = (int)tb.u_idx.size();
     D.ue_n = tb.ue_ptr.back();
@@ -517,12 +606,14 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
     D.u_idx = I + o.u_idx;
     D.u_coef = F + o.u_coef;
   }
+  P.tabd = (const TableDesc*)(F + X->o_tabd);
+  if (upload_tabd(X, st, true)) return fail(TDG_EHIP, "upload of the degree descriptors failed");
   if (set_kernel_smem_limit(T.n, (size_t)X->lp.total * 8 + 64)) return fail(TDG_EHIP, "cannot raise the LDS limit");
   {
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
     HIP_OK(hipDeviceGetAttribute(&X->ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    X->resident = resident_blocks_per_cu(T.n, X->lp.TPW, X->opts.precision == 1, (size_t)X->lp.total * 8);
+    X->resident = resident_blocks_per_cu(T.n, X->lp.moment ? 0 : X->lp.TPW, X->opts.precision == 1, (size_t)X->lp.total * 8);
   }
   // clear state, front, status, per-tent outputs
   if (launch_fill(P.state, 0.0, X->nq * (T.n + 2), stream) || launch_fill(P.tau, 0.0, T.nv, stream) ||
@@ -787,16 +878,48 @@ int trefftz_set_tuning(tdg_ctx* X, int32_t pts_per_chunk, int32_t persistent) {
     return fail(TDG_EINVAL, "pts_per_chunk must be 0, 4, 8, 16, 32 or 64");
   const LdsPlan old = X->lp;
   int rc = plan_lds(X, pts_per_chunk);
-  if (rc == TDG_OK && X->lp.A_in_lds != old.A_in_lds) rc = fail(TDG_EINVAL, "shape changes where the systems live");
+  if (rc == TDG_OK && !X->lp.A_in_lds && X->sys_stride == 0)
+    rc = fail(TDG_EINVAL, "shape puts the systems in global slots that were not allocated");
   if (rc != TDG_OK) {
     X->lp = old;
     return rc;
   }
+  X->forced_pch = pts_per_chunk;
   X->persistent = persistent;
   if (X->bound) {
+    if (upload_tabd(X, nullptr, false)) return fail(TDG_EHIP, "upload of the degree descriptors failed");
     if (set_kernel_smem_limit(X->topo.n, (size_t)X->lp.total * 8 + 64)) return fail(TDG_EHIP, "cannot raise the LDS limit");
-    X->resident = resident_blocks_per_cu(X->topo.n, X->lp.TPW, X->opts.precision == 1, (size_t)X->lp.total * 8);
+    X->resident = resident_blocks_per_cu(X->topo.n, X->lp.moment ? 0 : X->lp.TPW, X->opts.precision == 1, (size_t)X->lp.total * 8);
   }
+  return TDG_OK;
+}
+
+int trefftz_set_gram_mode(tdg_ctx* X, int32_t mode) {
+  if (!X) return fail(TDG_EINVAL, "NULL argument");
+  if (mode != 0 && mode != 1) return fail(TDG_EINVAL, "mode must be 0 or 1");
+  if (mode == 1 && X->opts.precision != 0) return fail(TDG_EINVAL, "the moment Gram is FP64 only");
+  const LdsPlan old = X->lp;
+  const int old_mode = X->gram_mode;
+  X->gram_mode = mode;
+  int rc = plan_lds(X, X->forced_pch);
+  if (rc == TDG_OK && !X->lp.A_in_lds && X->sys_stride == 0)
+    rc = fail(TDG_EINVAL, "mode puts the systems in global slots that were not allocated");
+  if (rc != TDG_OK) {
+    X->lp = old;
+    X->gram_mode = old_mode;
+    return rc;
+  }
+  if (X->bound) {
+    if (upload_tabd(X, nullptr, false)) return fail(TDG_EHIP, "upload of the degree descriptors failed");
+    if (set_kernel_smem_limit(X->topo.n, (size_t)X->lp.total * 8 + 64)) return fail(TDG_EHIP, "cannot raise the LDS limit");
+    X->resident = resident_blocks_per_cu(X->topo.n, X->lp.moment ? 0 : X->lp.TPW, X->opts.precision == 1, (size_t)X->lp.total * 8);
+  }
+  return TDG_OK;
+}
+
+int trefftz_get_gram_mode(const tdg_ctx* X, int32_t* mode) {
+  if (!X || !mode) return fail(TDG_EINVAL, "NULL argument");
+  *mode = X->gram_mode;
   return TDG_OK;
 }
 

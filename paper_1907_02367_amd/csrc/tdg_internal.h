@@ -28,7 +28,10 @@ constexpr int kNParam = kHid * kFeat + kHid + kHid * kHid + kHid + kOut * kHid +
 // for the non-constant functions j = 0..NW-1 (basis functions 1..N-1).
 // U table: CSR over rows j (basis function j+1).
 struct TableDesc {
-  int p, NW, M, M1, fo_nnz, u_nnz, ue_n, tr_n;
+  int p, NW, M, M1, M2, fo_nnz, u_nnz, ue_n, tr_n;
+  int pch, nwp, pci;  // execution plan at this degree: points per chunk, operand stride, face chunk
+  const int* expo2;  // M2*(n+1) exponents of the moment monomials (degree <= 2p-2)
+  const int* K2;     // M1*M1: moment index of the product of monomials k, l < M1
   // entry form: entries of basis function j+1 are ue_ptr[j]..ue_ptr[j+1]-1; entry e
   // holds (n+2) pairs (monomial index, coefficient) for U, v = dU/dt and
   // sigma_m = -dU/dx_m: ue_idx[e*(n+2)+s], ue_coef[e*(n+2)+s] (coefficient 0 if absent)
@@ -92,7 +95,7 @@ struct KParams {
   signed char* p_used;  // nullable: degree each tent was finally solved with
   double* work;   // global scratch for systems that do not fit in LDS
   long long work_stride;  // doubles per workgroup slot
-  TableDesc tab[kMaxP + 1];
+  const TableDesc* tabd;  // device array indexed by the degree (0 .. kMaxP)
 };
 
 // Device status bits (OR-ed by kernels)
@@ -121,11 +124,14 @@ struct LdsPlan {
   int tab_in_lds;
   int tab_int_dbl;  // doubles occupied by the integer part of a staged table
   int maxfaces;  // Dirichlet facets containing one vertex, at most
+  int moment;    // 1: Gram and right-hand sides from point moments of the monomials
+  int pci[kMaxP + 1];  // points per chunk of the interface faces at each degree
+  int mt_w1;     // moment mode: offset of the monomial table inside the W1 region
   int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, off_fg, off_AF, off_vec, total;
 };
 
 int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, int grid_n, int* ctr, void* stream);
-int resident_blocks_per_cu(int n, int tpw, bool mixed, size_t shm_bytes);
+int resident_blocks_per_cu(int n, int tpw, bool mixed, size_t shm_bytes);  // tpw 0: moment-mode kernel
 int set_kernel_smem_limit(int n, size_t bytes);
 int launch_fill(double* p, double v, long long n, void* stream);
 int launch_fill_i8(signed char* p, signed char v, long long n, void* stream);
@@ -160,7 +166,9 @@ void gauss_jacobi01(int q, int a, std::vector<double>& x, std::vector<double>& w
 Quadrature simplex_rule(int n, int q);
 
 struct Table {
-  int n = 0, p = 0, NW = 0, M = 0, M1 = 0;
+  int n = 0, p = 0, NW = 0, M = 0, M1 = 0, M2 = 0;
+  std::vector<int> expo2;  // M2*(n+1): exponents of the monomials of degree <= 2p-2
+  std::vector<int> K2;     // M1*M1: index in expo2 of the product of monomials k and l
   std::vector<int> parent, var;
   std::vector<int> expo;  // M*(n+1): k, alpha_1..alpha_n
   std::vector<int> fo_ptr, fo_idx;

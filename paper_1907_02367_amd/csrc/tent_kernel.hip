@@ -74,7 +74,17 @@ struct Tab {
   const int* tr_j;
   const double* tr_coef;
   const int* expo;  // M*(NS+1) exponents (k, alpha)
-  int NW, M, M1;
+  // moment mode (global memory): sparse fields per (function, component), U rows,
+  // moment monomials and the product index
+  const int* fo_ptr;
+  const int* fo_idx;
+  const double* fo_coef;
+  const int* u_ptr;
+  const int* u_idx;
+  const double* u_coef;
+  const int* expo2;
+  const int* K2;
+  int NW, M, M1, M2;
 };
 
 // Monomials of points [0, npt) from their coordinates var[pt*(NS+1) + v]
@@ -266,7 +276,186 @@ __device__ inline bool block_lu_solve(double* A, long long lda, int S, double* x
 
 // Solves one tent; called by every thread of the workgroup.  All early returns
 // are taken by the whole workgroup (their conditions are workgroup-uniform).
-template <int NS, int TPW, bool MIXED>
+
+// Gram block (r, r) of a tent from the moments NU (moment mode), one test
+// function i at a time:  Z[b][l] = sum over the terms (a, k, al) of function i
+// of al H_ab(k, l), then A_ij += sum over the terms (b, l, be) of function j of
+// be Z[b][l].  Top Gram (dirichlet = false): H_00 = H_dd = nu, H_0d = H_d0 =
+// -c nu_d (lower triangle computed, mirrored).  Dirichlet faces (dirichlet =
+// true): H_00 = alpha c^2 nu, H_0d = c nu_d (row v, column sigma_d), all j.
+template <int NS>
+__device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, const double* fo_coef,
+                                               const int* K2, int M1, int M2, int NW, const double* NU, double* Z,
+                                               double cr, double alpha, bool dirichlet, double* A, long long lda,
+                                               int row0) {
+  const int tid = threadIdx.x;
+  const double ca = alpha * cr * cr;
+  for (int i = 0; i < NW; ++i) {
+    for (int l = tid; l < M1; l += blockDim.x)
+      for (int c = 0; c <= NS; ++c) Z[c * M1 + l] = 0.0;
+    const int amax = dirichlet ? 0 : NS;
+    for (int a = 0; a <= amax; ++a) {
+      const int row = i * (NS + 1) + a;
+      for (int e = fo_ptr[row]; e < fo_ptr[row + 1]; ++e) {
+        const int k = fo_idx[e];
+        const double al = fo_coef[e];
+        const int* K2r = K2 + k * M1;
+        for (int l = tid; l < M1; l += blockDim.x) {
+          const int b2 = K2r[l];
+          if (dirichlet) {
+            Z[l] += ca * al * NU[b2];
+            for (int d = 0; d < NS; ++d) Z[(1 + d) * M1 + l] += cr * al * NU[(1 + d) * M2 + b2];
+          } else if (a == 0) {
+            Z[l] += al * NU[b2];
+            for (int d = 0; d < NS; ++d) Z[(1 + d) * M1 + l] -= cr * al * NU[(1 + d) * M2 + b2];
+          } else {
+            Z[a * M1 + l] += al * NU[b2];
+            Z[l] -= cr * al * NU[a * M2 + b2];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const int jmax = dirichlet ? NW - 1 : i;
+    for (int j = tid; j <= jmax; j += blockDim.x) {
+      double acc = 0.0;
+      for (int b = 0; b <= NS; ++b) {
+        const int row = j * (NS + 1) + b;
+        for (int e = fo_ptr[row]; e < fo_ptr[row + 1]; ++e) acc += fo_coef[e] * Z[b * M1 + fo_idx[e]];
+      }
+      A[(long long)(row0 + i) * lda + row0 + j] += acc;
+      if (!dirichlet && j != i) A[(long long)(row0 + j) * lda + row0 + i] += acc;
+    }
+    __syncthreads();
+  }
+}
+
+
+// Moments over the points of one speed group (moment mode): top moments of the
+// monomials of degree <= 2p-2 weighted by w and w g_d (NU), bottom moments of the
+// monomials of degree <= p weighted by w (BU) and by the incoming-data terms of
+// the right-hand side (BV), and the weight and U sums of the recovery row.
+template <int NS>
+__device__ inline void moment_points(const double* lam_ref, const double* w_ref, const double* state, int Q,
+                                           const double* EL, int ELS, const int* gel, int npts, const double* XV,
+                                           double cr, double hr, double tmid, double dt, int p, int PCH, int M1,
+                                           int M2, int Mm, const int* expo, const int* expo2, double* NU, double* BV,
+                                           double* BU, double* PV, double* PW, double* PD, double* PG, double* POWT,
+                                           double* POWB, double* A00r, double* r0r) {
+  const int tid = threadIdx.x;
+  const int E2 = 2 * p - 1;
+  const double ic2 = 1.0 / (cr * cr);
+  for (int i = tid; i < (NS + 1) * M2 + (NS + 1) * M1 + Mm; i += blockDim.x) NU[i] = 0.0;
+  double sw_acc = 0.0, su_acc = 0.0;
+  __syncthreads();
+  for (int f0 = 0; f0 < npts; f0 += PCH) {
+    const int nc = min(PCH, npts - f0);
+    for (int pt = tid; pt < nc; pt += blockDim.x) {
+      const int f = f0 + pt;
+      const int li = gel[f / Q];
+      const int q = f % Q;
+      const double* R = EL + li * ELS;
+      const int lV = (int)R[El<NS>::LV];
+      const int e = (int)R[El<NS>::E];
+      const double* lam = lam_ref + (size_t)q * (NS + 1);
+      double xt[NS], pho = 0.0;
+      for (int d = 0; d < NS; ++d) xt[d] = 0.0;
+      for (int k = 0; k <= NS; ++k) {
+        pho += lam[k] * R[El<NS>::TAU + k];
+        for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
+      }
+      const double phi = pho + lam[lV] * dt;
+      const double w = w_ref[q] * R[El<NS>::DET];
+      const double* st = state + (size_t)e * (NS + 2) * Q;
+      const double vb = st[q];
+      double sg = 0.0;
+      for (int d = 0; d < NS; ++d) sg += st[(1 + d) * Q + q] * R[El<NS>::GOLD + d];
+      PD[pt * (NS + 2)] = w * (ic2 * vb - sg);
+      for (int d = 0; d < NS; ++d) PD[pt * (NS + 2) + 1 + d] = w * (st[(1 + d) * Q + q] - vb * R[El<NS>::GOLD + d]);
+      PD[pt * (NS + 2) + NS + 1] = w * st[(NS + 1) * Q + q];
+      PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
+      PV[(PCH + pt) * (NS + 1)] = cr * (pho - tmid) / hr;
+      for (int d = 0; d < NS; ++d) {
+        const double xh = (xt[d] - XV[d]) / hr;
+        PV[pt * (NS + 1) + 1 + d] = xh;
+        PV[(PCH + pt) * (NS + 1) + 1 + d] = xh;
+        PG[pt * NS + d] = w * R[El<NS>::GNEW + d];
+      }
+      PW[pt] = w;
+    }
+    __syncthreads();
+    for (int i = tid; i < nc * (NS + 1); i += blockDim.x) {
+      const int pt = i / (NS + 1), v = i % (NS + 1);
+      double x = PV[pt * (NS + 1) + v], a = 1.0;
+      double* o = POWT + (pt * (NS + 1) + v) * E2;
+      for (int ee = 0; ee < E2; ++ee) {
+        o[ee] = a;
+        a *= x;
+      }
+      x = PV[(PCH + pt) * (NS + 1) + v];
+      a = 1.0;
+      o = POWB + (pt * (NS + 1) + v) * (p + 1);
+      for (int ee = 0; ee <= p; ++ee) {
+        o[ee] = a;
+        a *= x;
+      }
+    }
+    __syncthreads();
+    for (int b = tid; b < M2; b += blockDim.x) {
+      int ex[NS + 1];
+#pragma unroll
+      for (int v = 0; v <= NS; ++v) ex[v] = expo2[b * (NS + 1) + v];
+      double a0 = 0.0, ad[NS];
+#pragma unroll
+      for (int d = 0; d < NS; ++d) ad[d] = 0.0;
+      for (int pt = 0; pt < nc; ++pt) {
+        const double* pw = POWT + pt * (NS + 1) * E2;
+        double mv = pw[ex[0]];
+#pragma unroll
+        for (int v = 1; v <= NS; ++v) mv *= pw[v * E2 + ex[v]];
+        a0 += PW[pt] * mv;
+#pragma unroll
+        for (int d = 0; d < NS; ++d) ad[d] += PG[pt * NS + d] * mv;
+      }
+      NU[b] += a0;
+#pragma unroll
+      for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += ad[d];
+    }
+    for (int k = tid; k < Mm; k += blockDim.x) {
+      int ex[NS + 1];
+#pragma unroll
+      for (int v = 0; v <= NS; ++v) ex[v] = expo[k * (NS + 1) + v];
+      double bu = 0.0, bv[NS + 1];
+#pragma unroll
+      for (int c = 0; c <= NS; ++c) bv[c] = 0.0;
+      for (int pt = 0; pt < nc; ++pt) {
+        const double* pw = POWB + pt * (NS + 1) * (p + 1);
+        double mv = pw[ex[0]];
+#pragma unroll
+        for (int v = 1; v <= NS; ++v) mv *= pw[v * (p + 1) + ex[v]];
+        bu += PW[pt] * mv;
+#pragma unroll
+        for (int c = 0; c <= NS; ++c) bv[c] += mv * PD[pt * (NS + 2) + c];
+      }
+      BU[k] += bu;
+      if (k < M1)
+#pragma unroll
+        for (int c = 0; c <= NS; ++c) BV[c * M1 + k] += bv[c];
+    }
+    if (tid == blockDim.x - 1)
+      for (int pt = 0; pt < nc; ++pt) {
+        sw_acc += PW[pt];
+        su_acc += PD[pt * (NS + 2) + NS + 1];
+      }
+    __syncthreads();
+  }
+  if (tid == blockDim.x - 1) {
+    *A00r += sw_acc;
+    *r0r += su_acc;
+  }
+}
+
+template <int NS, int TPW, bool MIXED, bool MOM>
 __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, double* lds) {
   __shared__ int s_m, s_piv, s_err, s_goff[kMaxGroups + 1], s_conv;
   __shared__ double s_red[2 * kBlock / 64];
@@ -308,27 +497,40 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   for (int dtry = 0;; ++dtry) {
   const int p = min(p_in + dtry, P.pmax);
   // chunk size and operand stride of degree p (lower degrees take larger chunks)
-  const int PCH = L.pch[p];
+  const TableDesc& Dp = P.tabd[p];
+  const int PCH = Dp.pch;
   const int LD2 = 2 * PCH;  // row stride of the monomial table (top points, then bottom points)
-  const int NWP = L.nwp[p];
+  const int NWP = Dp.nwp;
   double* PV = lds + L.off_pt;    // 2*PCH x (NS+1): top then bottom coordinates
   double* PW = PV + 2 * PCH * (NS + 1);  // PCH weights
   double* PD = PW + PCH;                 // PCH x (NS+2): weighted bottom data, w*U_b
   double* PG = PD + PCH * (NS + 2);      // PCH x NS: grad phi_new at the point
   double* PS = PG + PCH * NS;            // PCH: c^-2 - |g_new|^2
   double* POW = lds + L.off_pow;         // 2*PCH x (NS+1) x (p+1)
-  double* MT = lds + L.off_mono;         // M x 2*PCH monomials (top points, then bottom points)
   double* W1 = lds + L.off_W1;           // PSI: PCH*(NS+1) rows, RB: PCH rows, UB: PCH rows (row stride NWP)
+  // M x 2*PCH monomials (top points, then bottom points); in moment mode this
+  // table lives in W1 behind the write-back coefficients
+  double* MT = MOM ? W1 + L.mt_w1 : lds + L.off_mono;
+  const int PCI = Dp.pci;  // points per chunk of the interface faces
   double* PSI = W1;
   double* RB = W1 + PCH * (NS + 1) * NWP;
   double* UB = RB + PCH * NWP;
   // ---- table of degree p (staged in LDS when it fits) ----------------------------
   Tab T;
   {
-    const TableDesc& D = P.tab[p];
+    const TableDesc& D = Dp;
     T.NW = D.NW;
     T.M = D.M;
     T.M1 = D.M1;
+    T.M2 = D.M2;
+    T.fo_ptr = D.fo_ptr;
+    T.fo_idx = D.fo_idx;
+    T.fo_coef = D.fo_coef;
+    T.u_ptr = D.u_ptr;
+    T.u_idx = D.u_idx;
+    T.u_coef = D.u_coef;
+    T.expo2 = D.expo2;
+    T.K2 = D.K2;
     if (L.tab_in_lds) {
       const int nue = D.ue_n, ntr = D.tr_n, nrow = (NS + 2) * D.M;
       int* ti = reinterpret_cast<int*>(lds + L.off_tab);
@@ -509,6 +711,46 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   }
   __syncthreads();
 
+  if constexpr (MOM) {
+    // ---- 2'. top Gram, bottom right-hand side and recovery rows from moments ------
+    // The fields are sparse combinations of the monomials m_k, k < M1, so over the
+    // top points  sum_q w [v_i v_j/c^2 + s_i.s_j - (v_i s_j + v_j s_i).g]  is a
+    // combination of the moments nu[b] = sum_q w m_b and nu_d[b] = sum_q w g_d m_b
+    // of the monomials b of degree <= 2p-2 (products m_k m_l = m_K2(k,l)); the
+    // right-hand side and the recovery row need the moments of m_k over the bottom
+    // points weighted by the incoming data.
+    const Tab& D = T;
+    const int M2 = T.M2, M1 = T.M1, Mm = T.M;
+    const int E2 = 2 * p - 1;  // top powers 0 .. 2p-2
+    double* NU = W1;                    // (NS+1) x M2: nu, nu_1..nu_n
+    double* BV = NU + (NS + 1) * M2;    // (NS+1) x M1: bottom moments times the data
+    double* BU = BV + (NS + 1) * M1;    // M: bottom moments sum w m_k
+    double* POWT = POW;
+    double* POWB = POW + PCH * (NS + 1) * E2;
+    for (int r = 0; r < m; ++r) {
+      const double cr = gc[r], hr = gh[r];
+      const double ic2 = 1.0 / (cr * cr);
+      const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
+      moment_points<NS>(P.lam_ref, P.w_ref, P.state, Q, EL, ELS, s_gel + s_goff[r], npts, XV, cr, hr, tmid, dt, p,
+                        PCH, M1, M2, Mm, T.expo, D.expo2, NU, BV, BU, PV, PW, PD, PG, POWT, POWB, A00 + r, r0 + r);
+      // right-hand side and recovery row of group r
+      for (int i = tid; i < NW; i += blockDim.x) {
+        double b = 0.0;
+        for (int a = 0; a <= NS; ++a) {
+          const int row = i * (NS + 1) + a;
+          const double sc = a == 0 ? cr : 1.0;
+          for (int e = D.fo_ptr[row]; e < D.fo_ptr[row + 1]; ++e) b += D.fo_coef[e] * sc * BV[a * M1 + D.fo_idx[e]];
+        }
+        A[(long long)(r * NW + i) * lda + S] += b;
+        double u = 0.0;
+        for (int e = D.u_ptr[i]; e < D.u_ptr[i + 1]; ++e) u += D.u_coef[e] * BU[D.u_idx[e]];
+        A0[r * NWP + i] += hr * u;
+      }
+      __syncthreads();
+      // Gram block (r, r) from the moments (Z reuses the bottom moments' space)
+      moment_gram_block<NS>(T.fo_ptr, T.fo_idx, T.fo_coef, T.K2, M1, M2, NW, NU, BV, cr, 0.0, false, A, lda, r * NW);
+    }
+  } else {
   // ---- 2. top Gram (matrix cores), bottom right-hand side, U recovery rows --------
   const int ntile_dim = (NW + 15) / 16;
   const int ntiles = ntile_dim * (ntile_dim + 1) / 2;
@@ -712,6 +954,8 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     __syncthreads();
   }
 
+  }  // quadrature Gram
+
   // ---- 3. time-like faces above facets containing V ---------------------------------
   const int nbf = P.vb_ptr[V + 1] - P.vb_ptr[V];
   const int nif = P.vi_ptr[V + 1] - P.vi_ptr[V];
@@ -805,6 +1049,105 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     __syncthreads();
     const long long gbase = P.bpt_off[tent];
     double* PN = PG;  // per-point outward normal (PCH x NS)
+    if constexpr (MOM) {
+      // Dirichlet terms from moments over the face points:
+      //   A_ij += sum_q w [alpha c^2 v_i v_j + c v_i (s_j.n)],  b_i += sum_q w g (alpha c v_i - s_i.n)
+      // (fields of the scaled basis; v = c vhat)
+      const Tab& D = T;
+      const int M2 = T.M2, M1 = T.M1;
+      const int E2 = 2 * p - 1;
+      double* NU = W1;                  // (NS+1) x M2: sum w m_b, sum w n_d m_b
+      double* BV = NU + (NS + 1) * M2;  // (NS+1) x M1: sum w g m_k, sum w g n_d m_k
+      double* POWT = POW;
+      for (int r = 0; r < m; ++r) {
+        const int nf = s_foff[r + 1] - s_foff[r];
+        if (nf == 0) continue;
+        const double cr = gc[r], hr = gh[r];
+        const int npts = nf * Q;
+        for (int i = tid; i < (NS + 1) * (M2 + M1); i += blockDim.x) NU[i] = 0.0;
+        __syncthreads();
+        for (int f0 = 0; f0 < npts; f0 += PCH) {
+          const int nc = min(PCH, npts - f0);
+          for (int pt = tid; pt < nc; pt += blockDim.x) {
+            const int fi = s_fl[s_foff[r] + (f0 + pt) / Q];
+            const int q = (f0 + pt) % Q;
+            const double* G0 = FG + fi * FGS;
+            const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+            double y[NS + 1];
+#pragma unroll
+            for (int d = 0; d <= NS; ++d) y[d] = 0.0;
+#pragma unroll
+            for (int k = 0; k <= NS; ++k)
+#pragma unroll
+              for (int d = 0; d <= NS; ++d) y[d] += lam[k] * G0[2 + NS + k * (NS + 1) + d];
+            const double w = P.w_ref[q] * G0[0];
+            PW[pt] = w;
+            PD[pt] = w * P.gD[gbase + (long long)fi * Q + q];
+#pragma unroll
+            for (int d = 0; d < NS; ++d) PN[pt * NS + d] = G0[2 + d];
+            PV[pt * (NS + 1)] = cr * (y[NS] - tmid) / hr;
+#pragma unroll
+            for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (y[d] - XV[d]) / hr;
+          }
+          __syncthreads();
+          for (int i = tid; i < nc * (NS + 1); i += blockDim.x) {
+            const int pt = i / (NS + 1), v = i % (NS + 1);
+            const double x = PV[pt * (NS + 1) + v];
+            double a = 1.0;
+            double* o = POWT + (pt * (NS + 1) + v) * E2;
+            for (int ee = 0; ee < E2; ++ee) {
+              o[ee] = a;
+              a *= x;
+            }
+          }
+          __syncthreads();
+          for (int b = tid; b < M2; b += blockDim.x) {
+            int ex[NS + 1];
+#pragma unroll
+            for (int v = 0; v <= NS; ++v) ex[v] = D.expo2[b * (NS + 1) + v];
+            double a0 = 0.0, ad[NS], g0 = 0.0, gd[NS];
+#pragma unroll
+            for (int d = 0; d < NS; ++d) ad[d] = gd[d] = 0.0;
+            for (int pt = 0; pt < nc; ++pt) {
+              const double* pw = POWT + pt * (NS + 1) * E2;
+              double mv = pw[ex[0]];
+#pragma unroll
+              for (int v = 1; v <= NS; ++v) mv *= pw[v * E2 + ex[v]];
+              const double wm = PW[pt] * mv, gm = PD[pt] * mv;
+              a0 += wm;
+              g0 += gm;
+#pragma unroll
+              for (int d = 0; d < NS; ++d) {
+                ad[d] += wm * PN[pt * NS + d];
+                gd[d] += gm * PN[pt * NS + d];
+              }
+            }
+            NU[b] += a0;
+#pragma unroll
+            for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += ad[d];
+            if (b < M1) {  // the first M1 moment monomials are the monomials of degree <= p-1
+              BV[b] += g0;
+#pragma unroll
+              for (int d = 0; d < NS; ++d) BV[(1 + d) * M1 + b] += gd[d];
+            }
+          }
+          __syncthreads();
+        }
+        for (int i = tid; i < NW; i += blockDim.x) {
+          double b = 0.0;
+          for (int a = 0; a <= NS; ++a) {
+            const int row = i * (NS + 1) + a;
+            const double sc = a == 0 ? P.alpha * cr : -1.0;
+            for (int e = D.fo_ptr[row]; e < D.fo_ptr[row + 1]; ++e)
+              b += D.fo_coef[e] * sc * BV[a * M1 + D.fo_idx[e]];
+          }
+          AT[(long long)(r * NW + i) * lda + S] += b;
+        }
+        __syncthreads();
+        moment_gram_block<NS>(T.fo_ptr, T.fo_idx, T.fo_coef, T.K2, M1, M2, NW, NU, BV, cr, P.alpha, true, AT, lda,
+                              r * NW);
+      }
+    } else {
     for (int r = 0; r < m; ++r) {
       const int nf = s_foff[r + 1] - s_foff[r];
       if (nf == 0) continue;
@@ -872,8 +1215,11 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
         __syncthreads();
       }
     }
+    }  // quadrature faces
   }
-  // 3b. speed interfaces, one face at a time
+  // 3b. speed interfaces, one face at a time (chunks of PCI points; in moment mode
+  //     the monomials sit in W1 behind the face values)
+  double* MTI = MOM ? W1 + 4 * PCI * NWP : MT;
   for (int f = nbf; f < nbf + nif; ++f) {
     const bool dir = false;
     int e1, k1, e2 = -1;
@@ -943,13 +1289,13 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     for (int d = 0; d < NS; ++d) nrm[d] = fsc[1 + d];
     const int ga = s_piv / 16, gb = s_piv % 16;
     const long long goff = P.bpt_off[tent] + (long long)f * Q;
-    for (int q0 = 0; q0 < Q; q0 += PCH) {
-      const int nc = min(PCH, Q - q0);
+    for (int q0 = 0; q0 < Q; q0 += PCI) {
+      const int nc = min(PCI, Q - q0);
       const int nside = dir ? 1 : 2;
       for (int side = 0; side < nside; ++side) {
         const int r = side == 0 ? ga : gb;
         const double cr = gc[r], hr = gh[r];
-        for (int pt = tid; pt < PCH; pt += blockDim.x) {
+        for (int pt = tid; pt < PCI; pt += blockDim.x) {
           double y[NS + 1];
           for (int d = 0; d < NS; ++d) y[d] = XV[d];
           y[NS] = tmid;
@@ -969,23 +1315,23 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
           PD[pt] = g;
         }
         __syncthreads();
-        monomials<NS>(T, T.M1, p, PV, POW, MT, PCH, PCH);
+        monomials<NS>(T, T.M1, p, PV, POW, MTI, PCI, PCI);
         __syncthreads();
-        for (int i = tid; i < PCH * NW; i += blockDim.x) {
-          const int pt = i % PCH, j = i / PCH;
+        for (int i = tid; i < PCI * NW; i += blockDim.x) {
+          const int pt = i % PCI, j = i / PCI;
           const double w = PW[pt], sw = sqrt(w), g = PD[pt];
           double fl[NS + 1], uu;
-          eval_j<NS, false>(T, j, MT, PCH, pt, fl, &uu);
+          eval_j<NS, false>(T, j, MTI, PCI, pt, fl, &uu);
           const double v = cr * fl[0];
           double sn = 0.0;
           for (int d = 0; d < NS; ++d) sn += fl[1 + d] * nrm[d];
           if (dir) {
             F1[pt * NWP + j] = sw * v;
-            F1[(PCH + pt) * NWP + j] = sw * (P.alpha * v + sn);
-            F1[(2 * PCH + pt) * NWP + j] = w * g * (P.alpha * v - sn);
+            F1[(PCI + pt) * NWP + j] = sw * (P.alpha * v + sn);
+            F1[(2 * PCI + pt) * NWP + j] = w * g * (P.alpha * v - sn);
           } else {
-            F1[((2 * side) * PCH + pt) * NWP + j] = sw * v;
-            F1[((2 * side + 1) * PCH + pt) * NWP + j] = sw * sn;
+            F1[((2 * side) * PCI + pt) * NWP + j] = sw * v;
+            F1[((2 * side + 1) * PCI + pt) * NWP + j] = sw * sn;
           }
         }
         __syncthreads();
@@ -994,12 +1340,12 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
         for (int idx = tid; idx < NW * NW; idx += blockDim.x) {
           const int ii = idx / NW, jj = idx % NW;
           double acc = 0.0;
-          for (int k = 0; k < nc; ++k) acc += F1[k * NWP + ii] * F1[(PCH + k) * NWP + jj];
+          for (int k = 0; k < nc; ++k) acc += F1[k * NWP + ii] * F1[(PCI + k) * NWP + jj];
           A[(long long)(ga * NW + ii) * lda + ga * NW + jj] += acc;
         }
         for (int j = tid; j < NW; j += blockDim.x) {
           double acc = 0.0;
-          for (int k = 0; k < nc; ++k) acc += F1[(2 * PCH + k) * NWP + j];
+          for (int k = 0; k < nc; ++k) acc += F1[(2 * PCI + k) * NWP + j];
           A[(long long)(ga * NW + j) * lda + S] += acc;
         }
       } else {
@@ -1009,10 +1355,10 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
           const int sa_i = blk / 2, sb_i = blk % 2;
           const double sa = sa_i ? -1.0 : 1.0, sb = sb_i ? -1.0 : 1.0;
           const int gA = sa_i ? gb : ga, gB = sb_i ? gb : ga;
-          const double* Va = F1 + (2 * sa_i) * PCH * NWP;
-          const double* Na = F1 + (2 * sa_i + 1) * PCH * NWP;
-          const double* Vb = F1 + (2 * sb_i) * PCH * NWP;
-          const double* Nb = F1 + (2 * sb_i + 1) * PCH * NWP;
+          const double* Va = F1 + (2 * sa_i) * PCI * NWP;
+          const double* Na = F1 + (2 * sa_i + 1) * PCI * NWP;
+          const double* Vb = F1 + (2 * sb_i) * PCI * NWP;
+          const double* Nb = F1 + (2 * sb_i + 1) * PCI * NWP;
           for (int idx = tid; idx < NW * NW; idx += blockDim.x) {
             const int ii = idx / NW, jj = idx % NW;
             double acc = 0.0;
@@ -1344,11 +1690,11 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
 // workgroup solves tent t0 + blockIdx.x; with a counter (persistent mode) a
 // resident grid takes tents in queue order from the counter until it passes
 // count (every workgroup exits after at most count + gridDim.x draws).
-template <int NS, int TPW, bool MIXED>
+template <int NS, int TPW, bool MIXED, bool MOM = false>
 __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L, int t0, int count, int* ctr) {
   extern __shared__ double lds[];
   if (ctr == nullptr) {
-    solve_tent<NS, TPW, MIXED>(P, L, t0 + blockIdx.x, lds);
+    solve_tent<NS, TPW, MIXED, MOM>(P, L, t0 + blockIdx.x, lds);
     return;
   }
   __shared__ int s_next;
@@ -1358,7 +1704,7 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     const int i = s_next;
     __syncthreads();
     if (i >= count) break;
-    solve_tent<NS, TPW, MIXED>(P, L, t0 + i, lds);
+    solve_tent<NS, TPW, MIXED, MOM>(P, L, t0 + i, lds);
     __syncthreads();
   }
 }
@@ -1382,7 +1728,9 @@ const void* kernel_ptr_mx(int tpw) {
 }
 
 template <int NS>
+// tpw = 0 selects the moment-mode kernel (FP64, no Gram tiles)
 const void* kernel_ptr(int tpw, bool mixed) {
+  if (tpw == 0) return (const void*)tent_layer_kernel<NS, 1, false, true>;
   return mixed ? kernel_ptr_mx<NS, true>(tpw) : kernel_ptr_mx<NS, false>(tpw);
 }
 
@@ -1390,6 +1738,10 @@ template <int NS, bool MX>
 hipError_t launch_mx(const KParams& P, const LdsPlan& L, int t0, int count, int grid_n, int* ctr, hipStream_t stream) {
   dim3 grid(grid_n), block(kBlock);
   size_t shm = (size_t)L.total * sizeof(double);
+  if (L.moment && !MX) {
+    hipLaunchKernelGGL((tent_layer_kernel<NS, 1, false, true>), grid, block, shm, stream, P, L, t0, count, ctr);
+    return hipGetLastError();
+  }
   switch (L.TPW) {
     case 1:
       hipLaunchKernelGGL((tent_layer_kernel<NS, 1, MX>), grid, block, shm, stream, P, L, t0, count, ctr);
@@ -1423,6 +1775,7 @@ hipError_t smem_ns(size_t bytes) {
   for (int mx = 0; mx < 2 && e == hipSuccess; ++mx)
     for (int tpw : {1, 2, 4, 8, 16})
       if (e == hipSuccess) e = hipFuncSetAttribute(kernel_ptr<NS>(tpw, mx == 1), a, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute(kernel_ptr<NS>(0, false), a, (int)bytes);
   return e;
 }
 

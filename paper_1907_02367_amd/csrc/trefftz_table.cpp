@@ -233,6 +233,28 @@ Table build_table(int n, int p) {
     }
     T.ue_ptr[j + 1] = (int)(T.ue_idx.size() / ns);
   }
+  // moment monomials (degree <= 2p-2, same order convention) and the index of
+  // the product of monomials k, l < M1 among them: the Gram of the fields is a
+  // combination of the moments of these products over the points
+  {
+    const int d2 = std::max(2 * p - 2, 0);
+    std::map<Key, int> index2;
+    for (int d = 0; d <= d2; ++d)
+      for (int k = d; k >= 0; --k)
+        for (Key al : multi(n, d - k)) {
+          al[0] = k;
+          index2[al] = (int)(T.expo2.size() / (n + 1));
+          for (int j = 0; j <= n; ++j) T.expo2.push_back(al[j]);
+        }
+    T.M2 = (int)(T.expo2.size() / (n + 1));
+    T.K2.assign((size_t)T.M1 * T.M1, 0);
+    for (int a = 0; a < T.M1; ++a)
+      for (int b = 0; b < T.M1; ++b) {
+        Key sum{0, 0, 0, 0};
+        for (int j = 0; j <= n; ++j) sum[j] = mono[a][j] + mono[b][j];
+        T.K2[(size_t)a * T.M1 + b] = index2.at(sum);
+      }
+  }
   // transposed form: rows comp*M + monomial
   {
     std::vector<std::vector<std::pair<int, double>>> rows((size_t)ns * T.M);

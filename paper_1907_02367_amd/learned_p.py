@@ -111,8 +111,9 @@ def load_default():
     return net
 
 
-def make_context(pr, p_max=None, precision=0, device=None):
-    """Library context of a workload (synthetic inputs resident on the GPU)."""
+def make_context(pr, p_max=None, precision=0, device=None, gram_mode=None):
+    """Library context of a workload (synthetic inputs resident on the GPU).
+    gram_mode None: the moment Gram in FP64 contexts, where it fits."""
     f = pr.data
     gamma = pr.gamma
     while True:  # a strongly jittered mesh may need a smaller edge-slope factor
@@ -125,6 +126,13 @@ def make_context(pr, p_max=None, precision=0, device=None):
             gamma *= 0.8
     ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max or pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta,
                       precision=precision)
+    mode = (1 if precision == 0 else 0) if gram_mode is None else gram_mode
+    if mode:
+        try:
+            ctx.set_gram_mode(mode)
+        except tdg.TdgError:
+            if gram_mode is not None:
+                raise
     xq, w = ctx.quad_points()
     ctx.set_initial(f.v(xq, 0.0), f.sigma(xq, 0.0), f.U(xq, 0.0))
     if ctx.nb:

@@ -66,6 +66,8 @@ EXPORTS = {
     "trefftz_table_info": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
     "trefftz_set_tuning": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32],
+    "trefftz_set_gram_mode": [ctypes.c_void_p, ctypes.c_int32],
+    "trefftz_get_gram_mode": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "trefftz_get_tuning": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)],
     "trefftz_capture_sweep": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
@@ -257,6 +259,7 @@ class Trefftz:
         _check(lib().trefftz_create(ctypes.byref(m), _ptr(c), tents._h, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
         self.p_max = int(p_max)
+        self.precision = int(precision)
         nq = ctypes.c_int64()
         _check(lib().trefftz_quad_points(h, ctypes.byref(nq), None, None))
         self.nq = nq.value
@@ -357,6 +360,14 @@ class Trefftz:
 
     def set_tuning(self, pts_per_chunk=0, persistent=0):
         _check(lib().trefftz_set_tuning(self._h, int(pts_per_chunk), int(persistent)))
+
+    def set_gram_mode(self, mode):
+        _check(lib().trefftz_set_gram_mode(self._h, int(mode)))
+
+    def get_gram_mode(self):
+        m = ctypes.c_int32()
+        _check(lib().trefftz_get_gram_mode(self._h, ctypes.byref(m)))
+        return m.value
 
     def get_tuning(self):
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

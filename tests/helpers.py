@@ -16,13 +16,15 @@ def oracle_for(pr, field=None, p=None, q=None):
     return o
 
 
-def gpu_for(pr, field=None, p_max=None, q=None, precision=0):
+def gpu_for(pr, field=None, p_max=None, q=None, precision=0, gram_mode=0):
     from paper_1907_02367_amd import tdg
 
     f = field or pr.data
     T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
     ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max or pr.p, q=q or pr.qpts,
                       alpha=pr.alpha, beta=pr.beta, precision=precision)
+    if gram_mode:
+        ctx.set_gram_mode(gram_mode)
     xq, w = ctx.quad_points()
     ctx.set_initial(f.v(xq, 0.0), f.sigma(xq, 0.0), f.U(xq, 0.0))
     if ctx.nb:

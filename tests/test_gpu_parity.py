@@ -48,15 +48,16 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("gram_mode", [0, 1], ids=["quadrature_gram", "moment_gram"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_full_run_matches_oracle(name):
+def test_full_run_matches_oracle(name, gram_mode):
     pr, field, q = CASES[name]()
     if pr.n == 3:
         pr.T = 0.25 if pr.p <= 3 else (0.1 if pr.p <= 5 else 0.03)
-    say(f"[gpu parity] {name}: n={pr.n} p={pr.p} ne={len(pr.elems)}")
+    say(f"[gpu parity] {name} gram mode {gram_mode}: n={pr.n} p={pr.p} ne={len(pr.elems)}")
     o = oracle_for(pr, field, q=q)
     o.run()
-    ctx, xq, w = gpu_for(pr, field, q=q)
+    ctx, xq, w = gpu_for(pr, field, q=q, gram_mode=gram_mode)
     ctx.layer_solve()
     v, s, U = ctx.read_state()
     ctx.status()
