@@ -58,7 +58,8 @@ struct tdg_ctx {
   std::vector<double> hf64;
   std::vector<int> hi32;
   struct TabOff {
-    size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx, ue_ptr, ue_idx, tr_ptr, tr_j, expo2, K2;  // i32
+    size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx, ue_ptr, ue_idx, tr_ptr, tr_j, expo2, K2, task2,
+        task1;  // i32
     size_t ue_coef, tr_coef;                                                           // f64
     size_t fo_coef, u_coef, fo_coef32;                 // f64 (fo_coef32: floats packed two per double)
   } toff[kMaxP + 1];
@@ -141,20 +142,23 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
     // moment mode: W1 holds the moments and the bottom data moments (the Z row of
     // the Gram reuses the latter), later the write-back coefficients with the
     // monomial table, or the interface face values
-    auto r4 = [](long long v) { return (v + 3) & ~3LL; };
     long long mom = 0;
     for (int p = 1; p <= pmax; ++p) {
       const Table& tb = X->tabs[p];
       mom = std::max(mom, (long long)(n + 1) * tb.M2 + (long long)(n + 1) * tb.M1 + tb.M);
+      mom = std::max(mom, (((long long)(n + 2) * tb.M + 3) & ~3LL) + ((long long)tb.ntask1 * kTaskInts + 1) / 2);
     }
-    L.mt_w1 = (int)r4((long long)(n + 2) * Tm.M);
+    for (int p = 1; p <= pmax; ++p)
+      if (X->tabs[p].ntask2 > kTaskSlots * kBlock || X->tabs[p].ntask1 > kTaskSlots1 * kBlock)
+        return fail(TDG_EINVAL, "too many moment tasks for the moment mode at this degree");
     for (const Choice& ch : order) {
       for (int pch : {64, 32, 16, 8, 4}) {
         if (forced_pch ? pch != forced_pch : pch < ch.min_pch) continue;
         L.PCH = pch;
         L.A_in_lds = ch.a;
         L.tab_in_lds = ch.t;
-        const long long w1 = std::max(mom, (long long)L.mt_w1 + (long long)Tm.M * 2 * pch);
+        // (sections 5 and 6 evaluate one point per thread: no monomial table)
+        const long long w1 = mom;
         long long pw_sz = 0;
         for (int p = 1; p <= pmax; ++p) {
           L.pch[p] = pch;
@@ -190,9 +194,13 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
   // per-point sizes (doubles) of the chunk regions at degree p with operand stride nwp
   auto pow_sz = [&](int p, long long c) { return 2LL * c * (n + 1) * (p + 1); };
   auto mono_sz = [&](int p, long long c) { return (long long)X->tabs[p].M * 2 * c; };
+  // W1 also holds the write-back coefficients and the degree-p monomial runs
+  auto wb_sz = [&](int p) {
+    return (((long long)(n + 2) * X->tabs[p].M + 3) & ~3LL) + ((long long)X->tabs[p].ntask1 * kTaskInts + 1) / 2;
+  };
   auto w1_sz = [&](int p, long long c) {
     const long long nwp = ((X->tabs[p].NW + 15) / 16) * 16 + 1;
-    return std::max<long long>(c * (n + 3) * nwp, (long long)(n + 2) * X->tabs[p].M);
+    return std::max<long long>(c * (n + 3) * nwp, wb_sz(p));
   };
   const long long pt_per = 2 * (n + 1) + 1 + (n + 2) + n + 1;
   for (int p = 0; p <= kMaxP; ++p) L.pch[p] = 0;
@@ -428,6 +436,8 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     o.tr_j = push(X->hi32, tb.tr_j.data(), tb.tr_j.size());
     o.expo2 = push(X->hi32, tb.expo2.data(), tb.expo2.size());
     o.K2 = push(X->hi32, tb.K2.data(), tb.K2.size());
+    o.task2 = push(X->hi32, tb.task2.data(), tb.task2.size());
+    o.task1 = push(X->hi32, tb.task1.data(), tb.task1.size());
     o.ue_coef = push(X->hf64, tb.ue_coef.data(), tb.ue_coef.size());
     o.tr_coef = push(X->hf64, tb.tr_coef.data(), tb.tr_coef.size());
     o.fo_coef = push(X->hf64, tb.fo_coef.data(), tb.fo_coef.size());
@@ -585,6 +595,10 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
     D.M2 = tb.M2;
     D.expo2 = I + o.expo2;
     D.K2 = I + o.K2;
+    D.task2 = I + o.task2;
+    D.task1 = I + o.task1;
+    D.ntask2 = tb.ntask2;
+    D.ntask1 = tb.ntask1;
     D.fo_nnz = (int)tb.fo_idx.size();
     D.u_nnz = (int)tb.u_idx.size();
     D.ue_n = tb.ue_ptr.back();

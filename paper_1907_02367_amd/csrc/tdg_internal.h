@@ -10,6 +10,13 @@
 namespace tdg {
 
 constexpr int kMaxP = 10;        // highest degree of U^p with tables
+// moment task (a run of up to 4 monomials that differ only in the exponent of the
+// last variable, consecutive): word 0 = prefix exponents e0 | e1 << 5 | e2 << 10
+// (variables 0..n-1) | first last-variable exponent << 15; words 1, 2 = the run's
+// monomial indices, 16 bits each (0xFFFF past the run)
+constexpr int kTaskInts = 3;
+constexpr int kTaskSlots = 6;   // moment-monomial tasks per thread held in registers (<= kTaskSlots * kBlock)
+constexpr int kTaskSlots1 = 2;  // tasks over the monomials of degree <= p, per thread
 constexpr int kMaxGroups = 8;    // speed groups inside one tent (Sec. 4.2)
 constexpr int kMaxPatch = 64;    // elements in one vertex patch
 constexpr int kMaxFaces = 64;    // Dirichlet facets containing one vertex
@@ -32,6 +39,9 @@ struct TableDesc {
   int pch, nwp, pci;  // execution plan at this degree: points per chunk, operand stride, face chunk
   const int* expo2;  // M2*(n+1) exponents of the moment monomials (degree <= 2p-2)
   const int* K2;     // M1*M1: moment index of the product of monomials k, l < M1
+  const int* task2;  // ntask2 moment tasks over the moment monomials (degree <= 2p-2)
+  const int* task1;  // ntask1 moment tasks over the monomials of degree <= p
+  int ntask2, ntask1;
   // entry form: entries of basis function j+1 are ue_ptr[j]..ue_ptr[j+1]-1; entry e
   // holds (n+2) pairs (monomial index, coefficient) for U, v = dU/dt and
   // sigma_m = -dU/dx_m: ue_idx[e*(n+2)+s], ue_coef[e*(n+2)+s] (coefficient 0 if absent)
@@ -126,7 +136,6 @@ struct LdsPlan {
   int maxfaces;  // Dirichlet facets containing one vertex, at most
   int moment;    // 1: Gram and right-hand sides from point moments of the monomials
   int pci[kMaxP + 1];  // points per chunk of the interface faces at each degree
-  int mt_w1;     // moment mode: offset of the monomial table inside the W1 region
   int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, off_fg, off_AF, off_vec, total;
 };
 
@@ -169,6 +178,8 @@ struct Table {
   int n = 0, p = 0, NW = 0, M = 0, M1 = 0, M2 = 0;
   std::vector<int> expo2;  // M2*(n+1): exponents of the monomials of degree <= 2p-2
   std::vector<int> K2;     // M1*M1: index in expo2 of the product of monomials k and l
+  std::vector<int> task2, task1;  // moment tasks (kTaskInts ints each) over expo2 and over expo
+  int ntask2 = 0, ntask1 = 0;
   std::vector<int> parent, var;
   std::vector<int> expo;  // M*(n+1): k, alpha_1..alpha_n
   std::vector<int> fo_ptr, fo_idx;

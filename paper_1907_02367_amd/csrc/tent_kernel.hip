@@ -84,7 +84,9 @@ struct Tab {
   const double* u_coef;
   const int* expo2;
   const int* K2;
-  int NW, M, M1, M2;
+  const int* task2;
+  const int* task1;
+  int NW, M, M1, M2, ntask2, ntask1;
 };
 
 // Monomials of points [0, npt) from their coordinates var[pt*(NS+1) + v]
@@ -335,11 +337,36 @@ __device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, c
 // monomials of degree <= 2p-2 weighted by w and w g_d (NU), bottom moments of the
 // monomials of degree <= p weighted by w (BU) and by the incoming-data terms of
 // the right-hand side (BV), and the weight and U sums of the recovery row.
+
+// Moment tasks of this thread (t = tid + s * blockDim.x), packed words in registers.
+template <int NSLOT>
+struct TaskRegs {
+  unsigned w0[NSLOT], w1[NSLOT], w2[NSLOT];
+};
+template <int NSLOT>
+__device__ inline void load_tasks(const int* task, int ntask, TaskRegs<NSLOT>& R) {
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int t = threadIdx.x + s * blockDim.x;
+    R.w0[s] = t < ntask ? (unsigned)task[t * kTaskInts] : 0u;
+    R.w1[s] = t < ntask ? (unsigned)task[t * kTaskInts + 1] : 0xFFFFFFFFu;
+    R.w2[s] = t < ntask ? (unsigned)task[t * kTaskInts + 2] : 0xFFFFFFFFu;
+  }
+}
+__device__ inline int task_exp(unsigned w0, int v) { return (int)((w0 >> (5 * v)) & 31u); }
+template <int NSLOT>
+__device__ inline int task_idx(const TaskRegs<NSLOT>& R, int s, int c) {
+  const unsigned w = c < 2 ? R.w1[s] : R.w2[s];
+  const unsigned i = (c & 1) ? (w >> 16) : (w & 0xFFFFu);
+  return i == 0xFFFFu ? -1 : (int)i;
+}
+
 template <int NS>
 __device__ inline void moment_points(const double* lam_ref, const double* w_ref, const double* state, int Q,
                                            const double* EL, int ELS, const int* gel, int npts, const double* XV,
                                            double cr, double hr, double tmid, double dt, int p, int PCH, int M1,
-                                           int M2, int Mm, const int* expo, const int* expo2, double* NU, double* BV,
+                                           int M2, int Mm, const int* task1, int ntask1, const int* task2,
+                                           int ntask2, double* NU, double* BV,
                                            double* BU, double* PV, double* PW, double* PD, double* PG, double* POWT,
                                            double* POWB, double* A00r, double* r0r) {
   const int tid = threadIdx.x;
@@ -347,6 +374,10 @@ __device__ inline void moment_points(const double* lam_ref, const double* w_ref,
   const double ic2 = 1.0 / (cr * cr);
   for (int i = tid; i < (NS + 1) * M2 + (NS + 1) * M1 + Mm; i += blockDim.x) NU[i] = 0.0;
   double sw_acc = 0.0, su_acc = 0.0;
+  TaskRegs<kTaskSlots> RT;
+  TaskRegs<kTaskSlots1> RB;
+  load_tasks(task2, ntask2, RT);
+  load_tasks(task1, ntask1, RB);
   __syncthreads();
   for (int f0 = 0; f0 < npts; f0 += PCH) {
     const int nc = min(PCH, npts - f0);
@@ -401,46 +432,97 @@ __device__ inline void moment_points(const double* lam_ref, const double* w_ref,
       }
     }
     __syncthreads();
-    for (int b = tid; b < M2; b += blockDim.x) {
-      int ex[NS + 1];
+    // top moments, one task (a run of up to 4 monomials that differ in the last
+    // exponent only) per slot: the shared prefix is formed once per point
 #pragma unroll
-      for (int v = 0; v <= NS; ++v) ex[v] = expo2[b * (NS + 1) + v];
-      double a0 = 0.0, ad[NS];
+    for (int sl = 0; sl < kTaskSlots; ++sl) {
+      if (tid + sl * (int)blockDim.x >= ntask2) break;
+      const unsigned w0 = RT.w0[sl];
+      int e[NS];
 #pragma unroll
-      for (int d = 0; d < NS; ++d) ad[d] = 0.0;
+      for (int v = 0; v < NS; ++v) e[v] = task_exp(w0, v);
+      const int d0 = task_exp(w0, 3);
+      double a0[4], ad[4][NS];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        a0[c] = 0.0;
+#pragma unroll
+        for (int d = 0; d < NS; ++d) ad[c][d] = 0.0;
+      }
+#pragma unroll 1
       for (int pt = 0; pt < nc; ++pt) {
         const double* pw = POWT + pt * (NS + 1) * E2;
-        double mv = pw[ex[0]];
+        double pre = pw[e[0]];
 #pragma unroll
-        for (int v = 1; v <= NS; ++v) mv *= pw[v * E2 + ex[v]];
-        a0 += PW[pt] * mv;
+        for (int v = 1; v < NS; ++v) pre *= pw[v * E2 + e[v]];
+        const double z = E2 > 1 ? pw[NS * E2 + 1] : 0.0;
+        double mv = pre * pw[NS * E2 + d0];
+        const double w = PW[pt];
+        double wg[NS];
 #pragma unroll
-        for (int d = 0; d < NS; ++d) ad[d] += PG[pt * NS + d] * mv;
+        for (int d = 0; d < NS; ++d) wg[d] = PG[pt * NS + d];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          a0[c] += w * mv;
+#pragma unroll
+          for (int d = 0; d < NS; ++d) ad[c][d] += wg[d] * mv;
+          mv *= z;
+        }
       }
-      NU[b] += a0;
 #pragma unroll
-      for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += ad[d];
+      for (int c = 0; c < 4; ++c) {
+        const int b = task_idx(RT, sl, c);
+        if (b < 0) continue;
+        NU[b] += a0[c];
+#pragma unroll
+        for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += ad[c][d];
+      }
     }
-    for (int k = tid; k < Mm; k += blockDim.x) {
-      int ex[NS + 1];
+    // bottom moments (monomials of degree <= p), same task scheme
 #pragma unroll
-      for (int v = 0; v <= NS; ++v) ex[v] = expo[k * (NS + 1) + v];
-      double bu = 0.0, bv[NS + 1];
+    for (int sl = 0; sl < kTaskSlots1; ++sl) {
+      if (tid + sl * (int)blockDim.x >= ntask1) break;
+      const unsigned w0 = RB.w0[sl];
+      int e[NS];
 #pragma unroll
-      for (int c = 0; c <= NS; ++c) bv[c] = 0.0;
+      for (int v = 0; v < NS; ++v) e[v] = task_exp(w0, v);
+      const int d0 = task_exp(w0, 3);
+      double bu[4], bv[4][NS + 1];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        bu[c] = 0.0;
+#pragma unroll
+        for (int q = 0; q <= NS; ++q) bv[c][q] = 0.0;
+      }
+#pragma unroll 1
       for (int pt = 0; pt < nc; ++pt) {
         const double* pw = POWB + pt * (NS + 1) * (p + 1);
-        double mv = pw[ex[0]];
+        double pre = pw[e[0]];
 #pragma unroll
-        for (int v = 1; v <= NS; ++v) mv *= pw[v * (p + 1) + ex[v]];
-        bu += PW[pt] * mv;
+        for (int v = 1; v < NS; ++v) pre *= pw[v * (p + 1) + e[v]];
+        const double z = pw[NS * (p + 1) + 1];
+        double mv = pre * pw[NS * (p + 1) + d0];
+        const double w = PW[pt];
+        double dd[NS + 1];
 #pragma unroll
-        for (int c = 0; c <= NS; ++c) bv[c] += mv * PD[pt * (NS + 2) + c];
+        for (int q = 0; q <= NS; ++q) dd[q] = PD[pt * (NS + 2) + q];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          bu[c] += w * mv;
+#pragma unroll
+          for (int q = 0; q <= NS; ++q) bv[c][q] += dd[q] * mv;
+          mv *= z;
+        }
       }
-      BU[k] += bu;
-      if (k < M1)
 #pragma unroll
-        for (int c = 0; c <= NS; ++c) BV[c * M1 + k] += bv[c];
+      for (int c = 0; c < 4; ++c) {
+        const int k = task_idx(RB, sl, c);
+        if (k < 0) continue;
+        BU[k] += bu[c];
+        if (k < M1)
+#pragma unroll
+          for (int q = 0; q <= NS; ++q) BV[q * M1 + k] += bv[c][q];
+      }
     }
     if (tid == blockDim.x - 1)
       for (int pt = 0; pt < nc; ++pt) {
@@ -452,6 +534,43 @@ __device__ inline void moment_points(const double* lam_ref, const double* w_ref,
   if (tid == blockDim.x - 1) {
     *A00r += sw_acc;
     *r0r += su_acc;
+  }
+}
+
+
+// Fields of the solution at one point from the monomial runs of the degree-p
+// table: val[c] += sum_k cm[c*M + k] m_k(var) for c <= NS over the monomials of
+// degree <= p-1 (v, sigma), and with WITH_U val[NS+1] over all monomials (U).
+// var = (th, xh_1..xh_n); the run loop and the coefficient addresses are the same
+// for every thread.
+template <int NS, bool WITH_U>
+__device__ inline void eval_runs(const Tab& T, const int* runs, const double* var, const double* cm, double* val) {
+  const int M = T.M, M1 = T.M1;
+  const double z = var[NS];
+  for (int t = 0; t < T.ntask1; ++t) {
+    const unsigned w0 = (unsigned)runs[t * kTaskInts];
+    const unsigned w1 = (unsigned)runs[t * kTaskInts + 1];
+    const unsigned w2 = (unsigned)runs[t * kTaskInts + 2];
+    double mv = 1.0;
+#pragma unroll
+    for (int v = 0; v < NS; ++v) {
+      const int ev = (int)((w0 >> (5 * v)) & 31u);
+      for (int i = 0; i < ev; ++i) mv *= var[v];
+    }
+    const int d0 = (int)((w0 >> 15) & 31u);
+    for (int i = 0; i < d0; ++i) mv *= z;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const unsigned ww = c < 2 ? w1 : w2;
+      const int k = (int)((c & 1) ? (ww >> 16) : (ww & 0xFFFFu));
+      if (k == 0xFFFF) break;
+      if (k < M1) {
+#pragma unroll
+        for (int comp = 0; comp <= NS; ++comp) val[comp] += cm[comp * M + k] * mv;
+      }
+      if (WITH_U) val[NS + 1] += cm[(NS + 1) * M + k] * mv;
+      mv *= z;
+    }
   }
 }
 
@@ -508,9 +627,8 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   double* PS = PG + PCH * NS;            // PCH: c^-2 - |g_new|^2
   double* POW = lds + L.off_pow;         // 2*PCH x (NS+1) x (p+1)
   double* W1 = lds + L.off_W1;           // PSI: PCH*(NS+1) rows, RB: PCH rows, UB: PCH rows (row stride NWP)
-  // M x 2*PCH monomials (top points, then bottom points); in moment mode this
-  // table lives in W1 behind the write-back coefficients
-  double* MT = MOM ? W1 + L.mt_w1 : lds + L.off_mono;
+  // M x 2*PCH monomials (top points, then bottom points) of the quadrature Gram
+  double* MT = MOM ? nullptr : lds + L.off_mono;
   const int PCI = Dp.pci;  // points per chunk of the interface faces
   double* PSI = W1;
   double* RB = W1 + PCH * (NS + 1) * NWP;
@@ -531,6 +649,10 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     T.u_coef = D.u_coef;
     T.expo2 = D.expo2;
     T.K2 = D.K2;
+    T.task2 = D.task2;
+    T.task1 = D.task1;
+    T.ntask2 = D.ntask2;
+    T.ntask1 = D.ntask1;
     if (L.tab_in_lds) {
       const int nue = D.ue_n, ntr = D.tr_n, nrow = (NS + 2) * D.M;
       int* ti = reinterpret_cast<int*>(lds + L.off_tab);
@@ -732,7 +854,8 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
       const double ic2 = 1.0 / (cr * cr);
       const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
       moment_points<NS>(P.lam_ref, P.w_ref, P.state, Q, EL, ELS, s_gel + s_goff[r], npts, XV, cr, hr, tmid, dt, p,
-                        PCH, M1, M2, Mm, T.expo, D.expo2, NU, BV, BU, PV, PW, PD, PG, POWT, POWB, A00 + r, r0 + r);
+                        PCH, M1, M2, Mm, T.task1, T.ntask1, T.task2, T.ntask2, NU, BV, BU, PV, PW, PD, PG, POWT,
+                        POWB, A00 + r, r0 + r);
       // right-hand side and recovery row of group r
       for (int i = tid; i < NW; i += blockDim.x) {
         double b = 0.0;
@@ -1059,6 +1182,10 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
       double* NU = W1;                  // (NS+1) x M2: sum w m_b, sum w n_d m_b
       double* BV = NU + (NS + 1) * M2;  // (NS+1) x M1: sum w g m_k, sum w g n_d m_k
       double* POWT = POW;
+      TaskRegs<kTaskSlots> RT;
+      TaskRegs<kTaskSlots1> RB;
+      load_tasks(T.task2, T.ntask2, RT);
+      load_tasks(T.task1, T.ntask1, RB);
       for (int r = 0; r < m; ++r) {
         const int nf = s_foff[r + 1] - s_foff[r];
         if (nf == 0) continue;
@@ -1101,34 +1228,96 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
             }
           }
           __syncthreads();
-          for (int b = tid; b < M2; b += blockDim.x) {
-            int ex[NS + 1];
+          // geometric moments (w, w n_d) over the moment monomials
 #pragma unroll
-            for (int v = 0; v <= NS; ++v) ex[v] = D.expo2[b * (NS + 1) + v];
-            double a0 = 0.0, ad[NS], g0 = 0.0, gd[NS];
+          for (int sl = 0; sl < kTaskSlots; ++sl) {
+            if (tid + sl * (int)blockDim.x >= T.ntask2) break;
+            const unsigned w0 = RT.w0[sl];
+            int e[NS];
 #pragma unroll
-            for (int d = 0; d < NS; ++d) ad[d] = gd[d] = 0.0;
+            for (int v = 0; v < NS; ++v) e[v] = task_exp(w0, v);
+            const int d0 = task_exp(w0, 3);
+            double a0[4], ad[4][NS];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              a0[c] = 0.0;
+#pragma unroll
+              for (int d = 0; d < NS; ++d) ad[c][d] = 0.0;
+            }
+#pragma unroll 1
             for (int pt = 0; pt < nc; ++pt) {
               const double* pw = POWT + pt * (NS + 1) * E2;
-              double mv = pw[ex[0]];
+              double pre = pw[e[0]];
 #pragma unroll
-              for (int v = 1; v <= NS; ++v) mv *= pw[v * E2 + ex[v]];
-              const double wm = PW[pt] * mv, gm = PD[pt] * mv;
-              a0 += wm;
-              g0 += gm;
+              for (int v = 1; v < NS; ++v) pre *= pw[v * E2 + e[v]];
+              const double z = E2 > 1 ? pw[NS * E2 + 1] : 0.0;
+              double mv = pre * pw[NS * E2 + d0];
+              const double w = PW[pt];
+              double nn[NS];
 #pragma unroll
-              for (int d = 0; d < NS; ++d) {
-                ad[d] += wm * PN[pt * NS + d];
-                gd[d] += gm * PN[pt * NS + d];
+              for (int d = 0; d < NS; ++d) nn[d] = w * PN[pt * NS + d];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                a0[c] += w * mv;
+#pragma unroll
+                for (int d = 0; d < NS; ++d) ad[c][d] += nn[d] * mv;
+                mv *= z;
               }
             }
-            NU[b] += a0;
 #pragma unroll
-            for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += ad[d];
-            if (b < M1) {  // the first M1 moment monomials are the monomials of degree <= p-1
-              BV[b] += g0;
+            for (int c = 0; c < 4; ++c) {
+              const int b = task_idx(RT, sl, c);
+              if (b < 0) continue;
+              NU[b] += a0[c];
 #pragma unroll
-              for (int d = 0; d < NS; ++d) BV[(1 + d) * M1 + b] += gd[d];
+              for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += ad[c][d];
+            }
+          }
+          // data moments (w g, w g n_d) over the monomials of degree <= p-1 (the
+          // first M1 monomials; runs starting beyond them are skipped)
+#pragma unroll
+          for (int sl = 0; sl < kTaskSlots1; ++sl) {
+            if (tid + sl * (int)blockDim.x >= T.ntask1) break;
+            if (task_idx(RB, sl, 0) >= M1) continue;
+            const unsigned w0 = RB.w0[sl];
+            int e[NS];
+#pragma unroll
+            for (int v = 0; v < NS; ++v) e[v] = task_exp(w0, v);
+            const int d0 = task_exp(w0, 3);
+            double g0[4], gd[4][NS];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              g0[c] = 0.0;
+#pragma unroll
+              for (int d = 0; d < NS; ++d) gd[c][d] = 0.0;
+            }
+#pragma unroll 1
+            for (int pt = 0; pt < nc; ++pt) {
+              const double* pw = POWT + pt * (NS + 1) * E2;
+              double pre = pw[e[0]];
+#pragma unroll
+              for (int v = 1; v < NS; ++v) pre *= pw[v * E2 + e[v]];
+              const double z = E2 > 1 ? pw[NS * E2 + 1] : 0.0;
+              double mv = pre * pw[NS * E2 + d0];
+              const double g = PD[pt];
+              double nn[NS];
+#pragma unroll
+              for (int d = 0; d < NS; ++d) nn[d] = g * PN[pt * NS + d];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                g0[c] += g * mv;
+#pragma unroll
+                for (int d = 0; d < NS; ++d) gd[c][d] += nn[d] * mv;
+                mv *= z;
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int k = task_idx(RB, sl, c);
+              if (k < 0 || k >= M1) continue;
+              BV[k] += g0[c];
+#pragma unroll
+              for (int d = 0; d < NS; ++d) BV[(1 + d) * M1 + k] += gd[c][d];
             }
           }
           __syncthreads();
@@ -1544,7 +1733,14 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
 
   // ---- 5. indicator: energy of the jump between the solution and the incoming
   //         trace on the bottom facets, 1/2 B_phi_old(u - u_b, u - u_b)
+  // Sections 5 and 6 evaluate the solution one point per thread: the monomials of
+  // a point come from the runs of the degree-p table (a shared prefix times
+  // consecutive powers of the last variable), the coefficients cm are read by all
+  // threads at the same address.
   double* cm = W1;  // (NS+2) x M: coefficients of v, sigma, U on the monomials, contracted with x
+  // the monomial runs of degree p, staged behind cm (read by all threads at once)
+  int* runs = reinterpret_cast<int*>(W1 + (((NS + 2) * T.M + 3) & ~3));
+  for (int i = tid; i < T.ntask1 * kTaskInts; i += blockDim.x) runs[i] = T.task1[i];
   const bool want_eta = P.indicator || !P.write_back || (P.eta_tol > 0.0 && p < P.pmax);
   if (want_eta) {
     double eta_loc = 0.0;
@@ -1559,52 +1755,34 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
       }
       __syncthreads();
       const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
-      for (int f0 = 0; f0 < npts; f0 += LD2) {
-        const int nc = min(LD2, npts - f0);
-        for (int pt = tid; pt < LD2; pt += blockDim.x) {
-          double xt[NS], phi = tmid;
-          for (int d = 0; d < NS; ++d) xt[d] = XV[d];
-          if (pt < nc) {
-            const int f = f0 + pt;
-            const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
-            const int q = f % Q;
-            const double* lam = P.lam_ref + (size_t)q * (NS + 1);
-            phi = 0.0;
-            for (int d = 0; d < NS; ++d) xt[d] = 0.0;
-            for (int k = 0; k <= NS; ++k) {
-              phi += lam[k] * R[El<NS>::TAU + k];
-              for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
-            }
-          }
-          PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
-          for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (xt[d] - XV[d]) / hr;
+      for (int f = tid; f < npts; f += blockDim.x) {
+        const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+        const int q = f % Q;
+        const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+        double xt[NS], phi = 0.0;
+        for (int d = 0; d < NS; ++d) xt[d] = 0.0;
+        for (int k = 0; k <= NS; ++k) {
+          phi += lam[k] * R[El<NS>::TAU + k];
+          for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
         }
-        __syncthreads();
-        monomials<NS>(T, T.M1, p, PV, POW, MT, LD2, LD2);
-        __syncthreads();
-        for (int pt = tid; pt < nc; pt += blockDim.x) {
-          const int f = f0 + pt;
-          const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
-          const int q = f % Q;
-          const int e = (int)R[El<NS>::E];
-          const double w = P.w_ref[q] * R[El<NS>::DET];
-          const double* st = P.state + (size_t)e * (NS + 2) * Q;
-          double val[NS + 1];
-          for (int comp = 0; comp <= NS; ++comp) {
-            double acc = 0.0;
-            for (int k = 0; k < T.M1; ++k) acc += cm[comp * T.M + k] * MT[k * LD2 + pt];
-            val[comp] = acc;
-          }
-          const double dv = cr * val[0] - st[q];
-          double ds2 = 0.0, dsg = 0.0;
-          for (int d = 0; d < NS; ++d) {
-            const double ds = val[1 + d] - st[(1 + d) * Q + q];
-            ds2 += ds * ds;
-            dsg += ds * R[El<NS>::GOLD + d];
-          }
-          eta_loc += 0.5 * w * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
+        double var[NS + 1];
+        var[0] = cr * (phi - tmid) / hr;
+        for (int d = 0; d < NS; ++d) var[1 + d] = (xt[d] - XV[d]) / hr;
+        double val[NS + 1];
+#pragma unroll
+        for (int c = 0; c <= NS; ++c) val[c] = 0.0;
+        eval_runs<NS, false>(T, runs, var, cm, val);
+        const int e = (int)R[El<NS>::E];
+        const double w = P.w_ref[q] * R[El<NS>::DET];
+        const double* st = P.state + (size_t)e * (NS + 2) * Q;
+        const double dv = cr * val[0] - st[q];
+        double ds2 = 0.0, dsg = 0.0;
+        for (int d = 0; d < NS; ++d) {
+          const double ds = val[1 + d] - st[(1 + d) * Q + q];
+          ds2 += ds * ds;
+          dsg += ds * R[El<NS>::GOLD + d];
         }
-        __syncthreads();
+        eta_loc += 0.5 * w * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
       }
     }
     // deterministic workgroup sum
@@ -1635,52 +1813,39 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     }
     __syncthreads();
     const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
-    for (int f0 = 0; f0 < npts; f0 += LD2) {
-      const int nc = min(LD2, npts - f0);
-      for (int pt = tid; pt < LD2; pt += blockDim.x) {
-        double xt[NS], phi = tmid;
-        for (int d = 0; d < NS; ++d) xt[d] = XV[d];
-        if (pt < nc) {
-          const int f = f0 + pt;
-          const int li = s_gel[s_goff[r] + f / Q];
-          const int q = f % Q;
-          const double* R = EL + li * ELS;
-          const int lV = (int)R[El<NS>::LV];
-          const double* lam = P.lam_ref + (size_t)q * (NS + 1);
-          phi = 0.0;
-          for (int d = 0; d < NS; ++d) xt[d] = 0.0;
-          for (int k = 0; k <= NS; ++k) {
-            phi += lam[k] * R[El<NS>::TAU + k];
-            for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
-          }
-          phi += lam[lV] * dt;
-        }
-        PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
-        for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (xt[d] - XV[d]) / hr;
+    for (int f = tid; f < npts; f += blockDim.x) {
+      const int li = s_gel[s_goff[r] + f / Q];
+      const int q = f % Q;
+      const double* R = EL + li * ELS;
+      const int lV = (int)R[El<NS>::LV];
+      const double* lam = P.lam_ref + (size_t)q * (NS + 1);
+      double xt[NS], phi = 0.0;
+      for (int d = 0; d < NS; ++d) xt[d] = 0.0;
+      for (int k = 0; k <= NS; ++k) {
+        phi += lam[k] * R[El<NS>::TAU + k];
+        for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
       }
-      __syncthreads();
-      monomials<NS>(T, T.M, p, PV, POW, MT, LD2, LD2);
-      __syncthreads();
-      for (int i = tid; i < nc * (NS + 2); i += blockDim.x) {
-        const int pt = i % nc, comp = i / nc;
-        double acc = 0.0;
-        if (comp <= NS) {
-          for (int k = 0; k < T.M1; ++k) acc += cm[comp * T.M + k] * MT[k * LD2 + pt];
-          if (comp == 0) acc *= cr;
-        } else {
-          acc = a0[r];
-          for (int k = 0; k < T.M; ++k) acc += cm[(NS + 1) * T.M + k] * MT[k * LD2 + pt];
-        }
-        const int f = f0 + pt;
-        const int li = s_gel[s_goff[r] + f / Q];
-        const int q = f % Q;
-        const int e = (int)EL[li * ELS + El<NS>::E];
-        P.state[((size_t)e * (NS + 2) + comp) * Q + q] = acc;
-        if (!isfinite(acc)) atomicOr(P.status, kStatNan);
-      }
-      __syncthreads();
+      phi += lam[lV] * dt;
+      double var[NS + 1];
+      var[0] = cr * (phi - tmid) / hr;
+      for (int d = 0; d < NS; ++d) var[1 + d] = (xt[d] - XV[d]) / hr;
+      double val[NS + 2];
+#pragma unroll
+      for (int c = 0; c < NS + 2; ++c) val[c] = 0.0;
+      eval_runs<NS, true>(T, runs, var, cm, val);
+      const int e = (int)R[El<NS>::E];
+      double* st = P.state + (size_t)e * (NS + 2) * Q;
+      st[q] = cr * val[0];
+#pragma unroll
+      for (int d = 0; d < NS; ++d) st[(1 + d) * Q + q] = val[1 + d];
+      st[(NS + 1) * Q + q] = a0[r] + val[NS + 1];
+      bool fin = true;
+#pragma unroll
+      for (int c = 0; c < NS + 2; ++c) fin = fin && isfinite(val[c]);
+      if (!fin) atomicOr(P.status, kStatNan);
     }
   }
+  __syncthreads();
   if (tid == 0) P.tau[V] = tt;
   break;
   }  // degree attempts

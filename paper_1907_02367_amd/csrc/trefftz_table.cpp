@@ -17,6 +17,7 @@
 #include <array>
 #include <map>
 #include <numeric>
+#include <stdexcept>
 
 #include "tdg_internal.h"
 
@@ -255,6 +256,41 @@ Table build_table(int n, int p) {
         T.K2[(size_t)a * T.M1 + b] = index2.at(sum);
       }
   }
+  // moment tasks: monomials sharing all exponents but the last, in runs of up to
+  // four consecutive last exponents (a thread forms the shared prefix once and
+  // steps the last variable), for the moment list (degree <= 2p-2) and for the
+  // monomials of degree <= p
+  auto tasks = [&](const std::vector<int>& ex, int count, std::vector<int>& out) {
+    std::map<std::array<int, 3>, std::vector<std::pair<int, int>>> runs;  // prefix -> (last exponent, index)
+    for (int i = 0; i < count; ++i) {
+      std::array<int, 3> pre{0, 0, 0};
+      for (int j = 0; j < n; ++j) pre[j] = ex[(size_t)i * (n + 1) + j];
+      runs[pre].push_back({ex[(size_t)i * (n + 1) + n], i});
+    }
+    for (auto& kv : runs) {
+      auto& v = kv.second;
+      std::sort(v.begin(), v.end());
+      for (size_t a = 0; a < v.size(); a += 4) {
+        const int cnt = (int)std::min<size_t>(4, v.size() - a);
+        // the run has consecutive last exponents
+        for (int c = 1; c < cnt; ++c)
+          if (v[a + c].first != v[a].first + c) throw std::runtime_error("moment run with a gap");
+        int idx[4];
+        for (int c = 0; c < 4; ++c) idx[c] = c < cnt ? v[a + c].second : 0xFFFF;
+        for (int c = 0; c < cnt; ++c)
+          if (idx[c] >= 0xFFFF) throw std::runtime_error("moment index beyond 16 bits");
+        const unsigned w0 = (unsigned)kv.first[0] | (unsigned)kv.first[1] << 5 | (unsigned)kv.first[2] << 10 |
+                            (unsigned)v[a].first << 15;
+        out.push_back((int)w0);
+        out.push_back((int)((unsigned)idx[0] | (unsigned)idx[1] << 16));
+        out.push_back((int)((unsigned)idx[2] | (unsigned)idx[3] << 16));
+      }
+    }
+  };
+  tasks(T.expo2, T.M2, T.task2);
+  T.ntask2 = (int)(T.task2.size() / kTaskInts);
+  tasks(T.expo, T.M, T.task1);
+  T.ntask1 = (int)(T.task1.size() / kTaskInts);
   // transposed form: rows comp*M + monomial
   {
     std::vector<std::vector<std::pair<int, double>>> rows((size_t)ns * T.M);
