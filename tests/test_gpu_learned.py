@@ -268,8 +268,7 @@ def test_trained_network_gains_over_fixed_pmax():
 
     pr = Cf.cfg5_cube_3d(m=18, p=8, seed=7, T=0.5, variant="b", regions=1)
     net = LP.load_default()
-    # Gram from the basis values at the points: the per-tent cost grows steeply with p
-    ctx, xq = LP.make_context(pr, gram_mode=0)
+    ctx, xq = LP.make_context(pr)  # FP64, moment Gram
     W = 12
     nt = int(ctx.tents.layer_ptr[W])
     say(f"[learned gain] m=18: {nt} tents in the first {W} layers")
@@ -287,7 +286,7 @@ def test_trained_network_gains_over_fixed_pmax():
     e_fixed = LP.front_error(ctx, pr.coords, pr.elems, xq, field=pr.data)[0]
     ctx.reset()
     holder = {}
-    t_learned = run(lambda: holder.update(b=LP.adaptive_sweep(ctx, net, -43.0, 10 * np.exp(-43.0), layer_end=W)))
+    t_learned = run(lambda: holder.update(b=LP.adaptive_sweep(ctx, net, -40.0, 10 * np.exp(-40.0), layer_end=W)))
     ctx.status()
     pu = holder["b"][2].cpu().numpy()[:nt]
     ps = holder["b"][1].cpu().numpy()[:nt]
