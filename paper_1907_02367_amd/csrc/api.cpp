@@ -105,6 +105,20 @@ int fail(int code, const std::string& msg) {
 // element-record size of the tent kernel (see El<NS> in the kernel)
 int el_size(int n) { return (n + 1) * n + (n + 1) + 2 * n + 5; }
 
+// Panel width of the blocked LU of a system held in global memory: the panel
+// and the U12 rows live in the chunk regions (points' powers, monomials,
+// operands), which hold nothing during the solve.
+void plan_lu_block(LdsPlan& L) {
+  L.lu_nb = 0;
+  if (L.A_in_lds) return;
+  const long long free_dbl = (long long)L.off_fg - L.off_pow;
+  for (int nb = 32; nb >= 4; nb -= 4)
+    if (lu_ws_doubles(L.S, nb) <= free_dbl) {
+      L.lu_nb = nb;
+      return;
+    }
+}
+
 int plan_lds(tdg_ctx* X, int forced_pch = 0) {
   const int n = X->topo.n;
   const Table& Tm = X->tabs[X->opts.p_max];
@@ -186,7 +200,10 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         L.off_AF = 0;
         L.off_vec = 0;
         L.total = off;
-        if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) return TDG_OK;
+        if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) {
+          plan_lu_block(L);
+          return TDG_OK;
+        }
       }
     }
     return fail(TDG_EINVAL, "tent kernel working set (moment mode) does not fit in LDS");
@@ -250,7 +267,10 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         L.off_AF = (mixed && ch.a) ? take((long long)L.S * L.lda) : 0;
         L.off_vec = mixed ? take(2LL * L.S) : 0;
         L.total = off;
-        if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) return TDG_OK;
+        if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) {
+          plan_lu_block(L);
+          return TDG_OK;
+        }
         // shrink the largest lower-degree chunk, if any is above the p_max chunk
         int pbig = 0;
         for (int p = 1; p < pmax; ++p)

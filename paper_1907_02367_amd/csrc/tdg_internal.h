@@ -136,8 +136,18 @@ struct LdsPlan {
   int maxfaces;  // Dirichlet facets containing one vertex, at most
   int moment;    // 1: Gram and right-hand sides from point moments of the monomials
   int pci[kMaxP + 1];  // points per chunk of the interface faces at each degree
+  int lu_nb;     // panel width of the blocked LU of a system in global memory (0: unblocked)
   int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, off_fg, off_AF, off_vec, total;
 };
+
+// LDS workspace (doubles) of the blocked LU of an S x (S+1) system with panels
+// of nb columns: the panel (column stride S|1), the U12 rows (row stride
+// (S+1)|1), then S + nb + 1 ints (row origins, pivots, one spare).
+constexpr int lu_ldp(int S) { return S | 1; }
+constexpr int lu_ldu(int S) { return (S + 1) | 1; }
+constexpr long long lu_ws_doubles(int S, int nb) {
+  return (long long)nb * (lu_ldp(S) + lu_ldu(S)) + (S + nb + 2) / 2;
+}
 
 int launch_layer(const KParams& P, const LdsPlan& L, int t0, int count, int grid_n, int* ctr, void* stream);
 int resident_blocks_per_cu(int n, int tpw, bool mixed, size_t shm_bytes);  // tpw 0: moment-mode kernel

@@ -242,7 +242,7 @@ __device__ inline bool block_lu_solve(double* A, long long lda, int S, double* x
           bi = oi;
         }
       }
-      if (tid == 0) *s_piv = bi;
+      if (tid == 0) *s_piv = bi < S ? bi : k;  // (a column of NaNs keeps its row)
     }
     __syncthreads();
     const int pr = *s_piv;
@@ -269,6 +269,208 @@ __device__ inline bool block_lu_solve(double* A, long long lda, int S, double* x
     const double xk = A[k * lda + S] / A[k * lda + k];
     if (tid == 0) x[k] = xk;
     for (int i = tid; i < k; i += blockDim.x) A[i * lda + S] -= A[i * lda + k] * xk;
+    __syncthreads();
+  }
+  return true;
+}
+
+// Blocked LU with partial pivoting of the augmented S x (S+1) matrix in global
+// memory (the workgroup's slot), then back substitution into x (LDS).  The
+// pivot rule is that of block_lu_solve (largest magnitude in the pivot column,
+// ties to the lower row); the elimination is organised in panels of nb columns
+// so that the trailing matrix is read and written once per panel rather than
+// once per column:
+//   1. rows k0..S-1 of the panel's columns are copied to LDS (column-major) and
+//      factored there: pivot search, exchange of whole panel rows, multipliers,
+//      rank-1 update of the panel's remaining columns;
+//   2. for each column right of the panel (the right-hand side included) one
+//      thread applies the panel's row exchanges and solves L11 u = a for the
+//      panel's rows: U12, kept in LDS and written back;
+//   3. A22 -= L21 U12 on the FP64 matrix cores (16x16 tiles, 4 terms per step);
+//   4. back substitution in blocks of nb rows from the bottom: one wave solves
+//      the diagonal block with its rows in registers, then every thread
+//      updates the right-hand sides of the rows above.
+// The multipliers below the panel's rows are not written back: the right-hand
+// side is carried as column S, and only U is read afterwards.  ws holds
+// lu_ws_doubles(S, nb) doubles; nb is a multiple of 4, at most 32.  Returns
+// false (for the whole workgroup) on a zero pivot.
+__device__ inline bool panel_lu_solve(double* A, long long lda, int S, int nb, double* x, double* ws) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  const int ldp = lu_ldp(S), ldu = lu_ldu(S);
+  double* Pn = ws;                                            // panel: Pn[j * ldp + r], r = row - k0
+  double* Ub = ws + (long long)nb * ldp;                      // U12: Ub[kk * ldu + c], column k0 + nbb + c
+  int* orig = reinterpret_cast<int*>(Ub + (long long)nb * ldu);  // orig[r]: old panel row now at position r
+  int* piv = orig + S;                                        // piv[kk]: position exchanged with kk
+  for (int k0 = 0; k0 < S; k0 += nb) {
+    const int nbb = min(nb, S - k0), R = S - k0;
+    // (loads batched ahead of the LDS stores)
+    for (int i0 = tid; i0 < R * nbb; i0 += 8 * blockDim.x) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u * blockDim.x, r = i / nbb, j = i - r * nbb;
+        v[u] = i < R * nbb ? A[(long long)(k0 + r) * lda + k0 + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u * blockDim.x, r = i / nbb, j = i - r * nbb;
+        if (i < R * nbb) Pn[j * ldp + r] = v[u];
+      }
+    }
+    for (int r = tid; r < R; r += blockDim.x) orig[r] = r;
+    __syncthreads();
+    for (int kk = 0; kk < nbb; ++kk) {
+      if (wave == 0) {
+        double best = -1.0;
+        int bi = R;
+        for (int r = kk + lane; r < R; r += 64) {
+          const double v = fabs(Pn[kk * ldp + r]);
+          if (v > best) {
+            best = v;
+            bi = r;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (lane == 0) piv[kk] = bi < R ? bi : kk;  // (a column of NaNs keeps its row)
+      }
+      __syncthreads();
+      const int pr = piv[kk];
+      if (pr != kk) {
+        for (int j = tid; j < nbb; j += blockDim.x) {
+          const double t = Pn[j * ldp + kk];
+          Pn[j * ldp + kk] = Pn[j * ldp + pr];
+          Pn[j * ldp + pr] = t;
+        }
+        if (tid == 0) {
+          const int t = orig[kk];
+          orig[kk] = orig[pr];
+          orig[pr] = t;
+        }
+      }
+      __syncthreads();
+      const double pv = Pn[kk * ldp + kk];
+      if (pv == 0.0) return false;
+      // one thread per row below the pivot: its multiplier, then its panel row
+      for (int r = kk + 1 + tid; r < R; r += blockDim.x) {
+        const double l = Pn[kk * ldp + r] / pv;
+        Pn[kk * ldp + r] = l;
+        for (int j = kk + 1; j < nbb; ++j) Pn[j * ldp + r] -= l * Pn[j * ldp + kk];
+      }
+      __syncthreads();
+    }
+    // U11 back to global memory (the diagonal block of the back substitution)
+    for (int i = tid; i < nbb * nbb; i += blockDim.x) {
+      const int r = i / nbb, j = i - r * nbb;
+      if (j >= r) A[(long long)(k0 + r) * lda + k0 + j] = Pn[j * ldp + r];
+    }
+    // U12, one thread per column: the exchanged column's entries at positions
+    // kk < nbb come from rows orig[kk]; the rows displaced below them (positions
+    // piv[kk] >= nbb) get entries of rows < nbb, which are overwritten only at
+    // the end, after every load of this column
+    const int r0 = k0 + nbb, W = S + 1 - r0;
+    for (int c = tid; c < W; c += blockDim.x) {
+      const long long col = r0 + c;
+      double v[32];
+#pragma unroll
+      for (int kk = 0; kk < 32; ++kk) v[kk] = kk < nbb ? A[(long long)(k0 + orig[kk]) * lda + col] : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 32; ++kk)
+        if (kk < nbb) Ub[kk * ldu + c] = v[kk];
+      for (int kk = 0; kk < nbb; ++kk) {
+        const int pos = piv[kk];
+        if (pos >= nbb) A[(long long)(k0 + pos) * lda + col] = A[(long long)(k0 + orig[pos]) * lda + col];
+      }
+      for (int kk = 0; kk < nbb; ++kk) {
+        double u = Ub[kk * ldu + c];
+        for (int m = 0; m < kk; ++m) u -= Pn[m * ldp + kk] * Ub[m * ldu + c];
+        Ub[kk * ldu + c] = u;
+        A[(long long)(k0 + kk) * lda + col] = u;
+      }
+    }
+    __syncthreads();
+    // A22 -= L21 U12: tile (ti, tj) covers rows r0 + 16 ti.., columns r0 + 16 tj..;
+    // lane l supplies L21[row l%16][k l/16] and U12[k l/16][column l%16], and
+    // element e of the result is row l/16 + 4e, column l%16
+    // (four tiles per wave at a time, their loads issued together)
+    const int nr = S - r0;
+    const int tr = (nr + 15) / 16, tc = (W + 15) / 16, nt = tr * tc;
+    for (int tb = wave * 4; tb < nt; tb += nwave * 4) {
+      d4 acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = min(tb + u, nt - 1);
+        const int i0 = r0 + (t / tc) * 16, jc = r0 + (t % tc) * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = i0 + (lane >> 4) + 4 * e;
+          acc[u][e] = (i < S && jc <= S) ? A[(long long)i * lda + jc] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = min(tb + u, nt - 1);
+        const int ia = r0 + (t / tc) * 16 + (lane & 15), jc = r0 + (t % tc) * 16 + (lane & 15);
+        for (int kq = 0; kq < nbb; kq += 4) {
+          const int kk = kq + (lane >> 4);
+          const double a = (ia < S && kk < nbb) ? -Pn[kk * ldp + (ia - k0)] : 0.0;
+          const double b = (jc <= S && kk < nbb) ? Ub[kk * ldu + (jc - r0)] : 0.0;
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (tb + u < nt) {
+          const int t = tb + u;
+          const int i0 = r0 + (t / tc) * 16, jc = r0 + (t % tc) * 16 + (lane & 15);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = i0 + (lane >> 4) + 4 * e;
+            if (i < S && jc <= S) A[(long long)i * lda + jc] = acc[u][e];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // back substitution
+  for (int i = tid; i < S; i += blockDim.x) x[i] = A[(long long)i * lda + S];
+  __syncthreads();
+  for (int kb = ((S - 1) / nb) * nb; kb >= 0; kb -= nb) {
+    const int nbb = min(nb, S - kb);
+    if (wave == 0) {
+      double r[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) r[j] = (lane < nbb && j < nbb) ? A[(long long)(kb + lane) * lda + kb + j] : 0.0;
+      double bi = lane < nbb ? x[kb + lane] : 0.0;
+#pragma unroll
+      for (int k = 31; k >= 0; --k) {
+        if (k < nbb) {
+          const double xk = readlane_d(bi, k) / readlane_d(r[k], k);
+          if (lane < k) bi -= r[k] * xk;
+          if (lane == k) bi = xk;
+        }
+      }
+      if (lane < nbb) x[kb + lane] = bi;
+    }
+    __syncthreads();
+    for (int i = tid; i < kb; i += blockDim.x) {
+      const double* row = A + (long long)i * lda + kb;
+      double v[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) v[j] = j < nbb ? row[j] : 0.0;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 32; ++j)
+        if (j < nbb) s += v[j] * x[kb + j];
+      x[i] -= s;
+    }
     __syncthreads();
   }
   return true;
@@ -1578,6 +1780,9 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
       if (wave == 0 && lane == 0 && !w_ok) s_err = kStatSingular;
       __syncthreads();
       ok = s_err == 0;
+    } else if (!L.A_in_lds && L.lu_nb > 0) {
+      ok = panel_lu_solve(A, lda, S, L.lu_nb, xs, lds + L.off_pow);
+      __syncthreads();
     } else {
       ok = block_lu_solve(A, lda, S, xs, &s_piv);
       __syncthreads();
