@@ -124,6 +124,66 @@ def test_cfg2_full_size_sampled_tents():
     assert er < 1e-2
 
 
+def test_cube_3d_p8_full_size_sampled_tents():
+    """The 3+1D workload of the learned-degree comparison at full size (93,750
+    tetrahedra, p = 8, moment Gram, FP64): the first 24 layers are swept on the
+    GPU, and sampled tents of three of them are re-solved by the oracle from
+    the GPU's state before that layer.  The oracle pitches only up to a time
+    above the tops of those layers (its pitcher is slow on 1.4M tents); the
+    tents of the first 24 layers do not depend on the final time, and the test
+    checks that both tent lists agree there."""
+    from paper_1907_02367_amd import tdg
+
+    # this seeded mesh is pitched causally from gamma = 0.4 x 0.8^4 on (the
+    # rule of the learned-degree tools: lower gamma by 0.8 until causal)
+    gamma = 0.4 * 0.8 ** 4
+    pr = C.cfg5_cube_3d(m=25, p=8, seed=7, T=0.5, variant="b", regions=1)
+    window = 24
+    say(f"[gpu parity] 3D cube full size sampled: ne={len(pr.elems)} p={pr.p}")
+    f = pr.data
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, gamma)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta)
+    ctx.set_gram_mode(1)
+    xq, _ = ctx.quad_points()
+    ctx.set_initial(f.v(xq, 0.0), f.sigma(xq, 0.0), f.U(xq, 0.0))
+    if ctx.nb:
+        bx = ctx.boundary_points()
+        ctx.set_boundary(f.v(bx[:, :-1], bx[:, -1]))
+    lp = ctx.tents.layer_ptr
+    glist = ctx.tents.as_list()[: lp[window]]
+    t_or = 1.5 * max(tt for _, _, tt in glist)
+    pr_or = C.cfg5_cube_3d(m=25, p=8, seed=7, T=t_or, variant="b", regions=1)
+    pr_or.gamma = gamma
+    o = oracle_for(pr_or, field=f)
+    assert o.tents[: lp[window]] == glist
+    assert list(o.layer_ptr[: window + 1]) == [int(x) for x in lp[: window + 1]]
+    rng = np.random.default_rng(1)
+    worst = 0.0
+    for l in range(window):
+        if l not in (0, 11, window - 1):
+            ctx.layer_solve(l, l + 1)
+            continue
+        v0, s0, U0 = ctx.read_state()
+        ctx.layer_solve(l, l + 1)
+        v1, s1, U1 = ctx.read_state()
+        o.v[...] = v0
+        o.sig[...] = s0
+        o.U[...] = U0
+        o.tau[:] = _front_before(o.tents, lp, l, len(pr.coords))
+        for i in rng.choice(np.arange(lp[l], lp[l + 1]), size=2, replace=False):
+            V, tb, tt = o.tents[i]
+            o.solve_tent(V, tb, tt)
+            els = o.topo.patch[V]
+            a = np.concatenate([v1[els].ravel(), s1[els].ravel()])
+            b = np.concatenate([o.v[els].ravel(), o.sig[els].ravel()])
+            r = max(rel_l2(a, b), rel_l2(U1[els], o.U[els]))
+            say(f"  layer {l} tent {i} (patch {len(els)}): rel diff {r:.2e}")
+            worst = max(worst, r)
+            assert r <= TOL_CASE["3d_p8_b_multipass_gram"], (l, V, r)
+    ctx.status()
+    say(f"  worst sampled rel diff {worst:.2e}")
+
+
 def test_polynomial_reproduction_full_size():
     pr = C.cfg2_plane_2d()
     f = F.PolynomialPlaneWaves(2, pr.p, 5, seed=11)
