@@ -4,14 +4,16 @@
 One step = one pass of the whole hot path over the workload: restore the
 initial values and the flat front (device to device), then solve every layer
 of tents from t = 0 to T (one launch per layer; all tents of a layer in that
-launch).  Inputs (mesh tables, initial values, boundary data) are resident in
-HBM before the timed region starts.
+launch).  The step is recorded once as a HIP graph and replayed; the same
+sweep launched layer by layer from the host is timed too (informational).
+Inputs (mesh tables, initial values, boundary data) are resident in HBM
+before the timed region starts.
 
 value = DOF-updates per second = sum over tents of dim U^p / wall time of a step.
 The roofline object reports the tent kernel: algorithmic FP64 flops per launch
 (the operation count of the method, not the kernel's padded work) divided by
-its average launch duration, measured with HIP events on the launch stream
-around every launch in the timed region.
+its average launch duration: HIP events on the replay stream around every
+timed replay, divided by the launches of the sweep.
 
 cpu_baseline: the CPU oracle (plain NumPy, one process) on a bounded prefix of
 the same workload, on this machine's host.
@@ -255,23 +257,33 @@ def main():
     torch.cuda.synchronize()
     del calib, calib2
     say(f"shape {ctx.get_tuning()}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    say("warm-up done")
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(L)]
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(ev[s])
-    torch.cuda.synchronize()
+    # The step: the whole sweep (reset to the initial data, then every layer,
+    # one launch each) recorded once as a HIP graph on a side stream and
+    # replayed; HIP events on that stream bracket every replay, and the average
+    # launch duration is a replay's event time over its launches (the gaps
+    # between the graph's kernels included).
+    gstream = torch.cuda.Stream()
+    gptr = gstream.cuda_stream
+    with torch.cuda.stream(gstream):
+        ctx.capture_sweep(0, L, with_reset=True, stream=gptr)
+        for _ in range(args.warmup):
+            ctx.replay_sweep(gptr)
+        torch.cuda.synchronize()
+        say("graph captured, warm-up done")
+        gev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            gev[s][0].record(gstream)
+            ctx.replay_sweep(gptr)
+            gev[s][1].record(gstream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     say(f"{args.steps} timed steps done")
-    wall = time.perf_counter() - t0
     ctx.status()
     ms_per_step = 1e3 * wall / args.steps
-    kern_ms = np.array([[ev[s][l][0].elapsed_time(ev[s][l][1]) for l in range(L)] for s in range(args.steps)])
-    avg_launch_s = kern_ms.mean() * 1e-3
+    step_ev_ms = np.array([gev[s][0].elapsed_time(gev[s][1]) for s in range(args.steps)])
+    avg_launch_s = step_ev_ms.mean() * 1e-3 / L
     flops_per_launch = layer_flops.mean()
     achieved = flops_per_launch / avg_launch_s
     if pr.exact:
@@ -279,18 +291,19 @@ def main():
     else:  # no closed-form solution: report the energy on the final front instead
         e_abs = e_rel = None
     E_T, _ = ctx.energy()
-    # the same sweep recorded once as a HIP graph and replayed (informational)
-    gstream = torch.cuda.Stream()
-    with torch.cuda.stream(gstream):
-        ctx.capture_sweep(0, L, with_reset=True, stream=gstream.cuda_stream)
-        for _ in range(args.warmup):
-            ctx.replay_sweep(gstream.cuda_stream)
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.replay_sweep(gstream.cuda_stream)
-        torch.cuda.synchronize()
-        graph_ms = 1e3 * (time.perf_counter() - g0) / args.steps
+    # the same sweep launched layer by layer from the host, with events around
+    # every launch (informational: launch gaps and per-launch kernel times)
+    for _ in range(args.warmup):
+        step()
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(L)]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - e0) / args.steps
+    kern_ms = np.array([[ev[s][l][0].elapsed_time(ev[s][l][1]) for l in range(L)] for s in range(args.steps)])
     ctx.status()
     dofs = float(N.sum())
     out = {
@@ -310,8 +323,10 @@ def main():
             "workload": desc,
             "tents": int(tents.n_tents), "layers": int(L), "dofs_per_tent_mean": float(N.mean()),
             "dof_updates_per_step": dofs, "e_abs_at_T": e_abs, "e_rel_at_T": e_rel, "energy_at_T": E_T,
-            "kernel_ms_per_step": float(kern_ms.sum(axis=1).mean()),
-            "graph_replay_ms_per_step": graph_ms,
+            "step": "HIP-graph replay of the sweep (reset + one launch per layer)",
+            "eager_ms_per_step": eager_ms,
+            "eager_kernel_ms_per_step": float(kern_ms.sum(axis=1).mean()),
+            "eager_avg_launch_us": float(kern_ms.mean() * 1e3),
             "kernel_shape": shape, "autotuned": tuned is not None,
             "autotune_ms_first_layers": tune_ms,
             "parallelism": "single GPU, all tents of a layer in one launch",
