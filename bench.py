@@ -51,6 +51,12 @@ def workload(name):
         desc = ("2+1D heterogeneous uneven batch: unit square, mesh aligned with x=0.5 "
                 f"({len(pr.elems)} triangles), c=1 (x<0.5) / 3 (x>0.5), p=4 (25 per speed group, 50 on "
                 "interface tents), Gaussian pulse width 0.05 at a seeded centre, homogeneous Dirichlet, T=1")
+    elif name in ("lshape", "lshape_graded"):
+        graded = name == "lshape_graded"
+        pr = C.lshape_2d(0.06 if graded else 0.01, graded)
+        desc = (f"2+1D L-shaped domain (Sec. 6.6), {'corner-graded' if graded else 'uniform'} structured mesh, "
+                f"h_max={pr.meta['h_max']} ({len(pr.elems)} triangles), c=1, p=3, corner Bessel solution "
+                "nu=2/3, a=10, T=1")
     elif name.startswith("cfg3"):
         p = int(name.split("p")[-1]) if "p" in name else 8
         pr = C.cfg3_precision_2d(p=p)

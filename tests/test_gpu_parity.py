@@ -45,6 +45,9 @@ CASES = {
     "3d_p5_b": lambda: (C.cfg5_cube_3d(m=2, p=5, variant="b"), None, None),
     "3d_p3_a_8groups_global_system": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="a", regions=2), None, None),
     "3d_p8_b_multipass_gram": lambda: (C.cfg5_cube_3d(m=2, p=8, variant="b"), None, None),
+    # the L-shaped domain of Sec. 6.6 with the corner Bessel data, uniform and graded
+    "2d_lshape_uniform_p3": lambda: (C.lshape_2d(0.5, False, T=0.5), None, None),
+    "2d_lshape_graded_p3": lambda: (C.lshape_2d(0.4, True, T=0.2), None, None),
 }
 
 

@@ -81,6 +81,31 @@ def cfg4_interface_2d(m: int = 159, p: int = 4, seed: int = 0, T: float = 1.0,
     return pr
 
 
+def lshape_2d(h_max: float = 0.05, graded: bool = False, p: int = 3, T: float = 1.0, a: float = 10.0):
+    """2+1D L-shaped domain of Sec. 6.6 (the paper's only timed experiment):
+    Omega = [-1,1]^2 minus (0,1] x [-1,0), c = 1, p = 3, T = 1, the corner
+    Bessel solution with nu = 2/3, a = 10 (g_D = its v on the boundary).
+    The paper meshes with an unstructured generator; here a structured
+    triangulation stands in: uniform with element diameter h_max, or graded
+    towards the corner with the size law h_K ~ h_max r^(2/3) (mu = 1/3), the
+    same largest diameter and the paper's smallest size h_min = h_max^3."""
+    beta = 3.0
+    rho0 = 0.0
+    if graded:
+        # the outermost squares are stretched by beta along the rays
+        m = int(np.ceil(2.0 * beta * np.sqrt(2.0) / h_max))
+        m += m % 2
+        rho0 = (h_max ** beta / (2.0 / m * np.sqrt(2.0))) ** (1.0 / (beta - 1.0))
+    else:
+        m = int(np.ceil(2.0 * np.sqrt(2.0) / h_max))
+        m += m % 2
+    coords, elems = M.lshape(m, graded=graded, beta=beta, rho0=rho0)
+    pr = Problem(f"2d_lshape_{'g' if graded else 'u'}_m{m}_p{p}", coords, elems, np.ones(len(elems)), p, T, 0.5,
+                 F.CornerBessel(a))
+    pr.meta.update(h_max=h_max, graded=graded, m=m)
+    return pr
+
+
 def cfg5_cube_3d(m: int = 25, p: int = 8, seed: int = 0, T: float = 0.5,
                  variant: str = "a", regions: int = 5):
     """3+1D: unit cube, m^3 cubes x 6 Kuhn tetrahedra (m = 25: 93,750 tets),

@@ -241,6 +241,49 @@ class SinProduct(Field):
         return out
 
 
+class CornerBessel(Field):
+    """U = cos(a t) sin(nu phi) J_nu(a r) in polar coordinates about the
+    origin, phi in [0, 2 pi) (Sec. 6.6: nu = 2/3, a = 10 on the L-shaped
+    domain, where phi runs over [0, 3 pi/2] and U vanishes on both edges at
+    the re-entrant corner).  J_nu(a r) sin(nu phi) is an eigenfunction of the
+    Laplacian with eigenvalue -a^2, so U solves the wave equation with c = 1;
+    grad U ~ r^(nu - 1) is singular at the corner."""
+
+    def __init__(self, a: float = 10.0, nu: float = 2.0 / 3.0):
+        self.a = float(a)
+        self.nu = float(nu)
+
+    def _polar(self, x):
+        r = np.hypot(x[..., 0], x[..., 1])
+        phi = np.mod(np.arctan2(x[..., 1], x[..., 0]), 2.0 * np.pi)
+        return r, phi
+
+    def U(self, x, t):
+        from scipy.special import jv
+
+        r, phi = self._polar(x)
+        return np.cos(self.a * t) * np.sin(self.nu * phi) * jv(self.nu, self.a * r)
+
+    def v(self, x, t):
+        from scipy.special import jv
+
+        r, phi = self._polar(x)
+        return -self.a * np.sin(self.a * t) * np.sin(self.nu * phi) * jv(self.nu, self.a * r)
+
+    def sigma(self, x, t):
+        from scipy.special import jv, jvp
+
+        r, phi = self._polar(x)
+        rs = np.where(r > 0.0, r, 1.0)
+        dr = self.a * jvp(self.nu, self.a * r) * np.sin(self.nu * phi)           # dS/dr
+        dp = np.where(r > 0.0, self.nu * np.cos(self.nu * phi) * jv(self.nu, self.a * r) / rs, 0.0)  # (1/r) dS/dphi
+        cp, sp = np.cos(phi), np.sin(phi)
+        gx = dr * cp - dp * sp
+        gy = dr * sp + dp * cp
+        ct = np.asarray(np.cos(self.a * t))
+        return -np.stack([gx * ct, gy * ct], axis=-1)
+
+
 class Zero(Field):
     def U(self, x, t):
         return np.zeros(x.shape[:-1])

@@ -105,6 +105,50 @@ def split_square(m: int, jitter: float = 0.2, seed: int = 0):
     return pts, _sort_elems(simp).astype(np.int32)
 
 
+def lshape(m: int, graded: bool = False, beta: float = 3.0, rho0: float = 0.0):
+    """Structured triangulation of the L-shaped domain [-1,1]^2 minus
+    (0,1] x [-1,0) (the domain of Sec. 6.6): a grid of m x m squares of side
+    2/m (m even, so that the axes are grid lines) without the squares of the
+    removed quadrant, each square cut along a diagonal whose direction
+    alternates like a checkerboard.  ``graded`` maps every vertex x to
+    x |x|_inf^(beta - 1): rays from the re-entrant corner and the outer square
+    are kept, and an element at distance r from the corner gets a size of
+    about beta (2/m) r^(1 - 1/beta) (beta = 3 is the paper's mu = 1/3).
+    Inside |x|_inf < rho0 the factor is held at rho0^(beta - 1), so the
+    smallest elements there have the size rho0^(beta - 1) (2/m) sqrt 2 (the
+    paper's floor h_min).  The map preserves orientation: with
+    g = max(rho, rho0)^(beta - 1) > 0 its Jacobian determinant is
+    g (g + rho g') > 0."""
+    assert m % 2 == 0 and m >= 2
+    g = np.linspace(-1.0, 1.0, m + 1)
+    X, Y = np.meshgrid(g, g, indexing="ij")  # X[i, j] = g[i]
+    half = m // 2
+    keep_cell = np.ones((m, m), bool)
+    keep_cell[half:, :half] = False  # cells with x > 0 and y < 0
+    keep_vert = np.zeros((m + 1, m + 1), bool)
+    for di in (0, 1):
+        for dj in (0, 1):
+            keep_vert[di:m + di, dj:m + dj] |= keep_cell
+    vid = -np.ones((m + 1, m + 1), np.int64)
+    vid[keep_vert] = np.arange(int(keep_vert.sum()))
+    pts = np.stack([X[keep_vert], Y[keep_vert]], axis=1)
+    tris = []
+    for i in range(m):
+        for j in range(m):
+            if not keep_cell[i, j]:
+                continue
+            a, b, c, d = vid[i, j], vid[i + 1, j], vid[i + 1, j + 1], vid[i, j + 1]
+            if (i + j) % 2 == 0:
+                tris += [(a, b, c), (a, c, d)]
+            else:
+                tris += [(a, b, d), (b, c, d)]
+    elems = np.array(tris, dtype=np.int64)
+    if graded:
+        rho = np.maximum(np.abs(pts).max(axis=1), rho0)
+        pts = pts * (rho ** (beta - 1.0))[:, None]
+    return pts, _sort_elems(elems).astype(np.int32)
+
+
 # The six Kuhn simplices of the unit cube: each follows a monotone lattice path
 # from corner (0,0,0) to (1,1,1), adding one unit vector per step.
 _KUHN_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
