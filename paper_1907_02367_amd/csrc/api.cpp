@@ -105,12 +105,12 @@ int fail(int code, const std::string& msg) {
 // element-record size of the tent kernel (see El<NS> in the kernel)
 int el_size(int n) { return (n + 1) * n + (n + 1) + 2 * n + 5; }
 
-// Panel width of the blocked LU of a system held in global memory: the panel
-// and the U12 rows live in the chunk regions (points' powers, monomials,
-// operands), which hold nothing during the solve.
-void plan_lu_block(LdsPlan& L) {
+// Panel width of the blocked LU of a system held in global memory (3+1D
+// kernels): the panel and the U12 rows live in the chunk regions (points'
+// powers, monomials, operands), which hold nothing during the solve.
+void plan_lu_block(LdsPlan& L, int n) {
   L.lu_nb = 0;
-  if (L.A_in_lds) return;
+  if (L.A_in_lds || n != 3) return;
   const long long free_dbl = (long long)L.off_fg - L.off_pow;
   for (int nb = 32; nb >= 4; nb -= 4)
     if (lu_ws_doubles(L.S, nb) <= free_dbl) {
@@ -201,7 +201,7 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         L.off_vec = 0;
         L.total = off;
         if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) {
-          plan_lu_block(L);
+          plan_lu_block(L, n);
           return TDG_OK;
         }
       }
@@ -268,7 +268,7 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         L.off_vec = mixed ? take(2LL * L.S) : 0;
         L.total = off;
         if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) {
-          plan_lu_block(L);
+          plan_lu_block(L, n);
           return TDG_OK;
         }
         // shrink the largest lower-degree chunk, if any is above the p_max chunk

@@ -1780,12 +1780,22 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
       if (wave == 0 && lane == 0 && !w_ok) s_err = kStatSingular;
       __syncthreads();
       ok = s_err == 0;
-    } else if (!L.A_in_lds && L.lu_nb > 0) {
-      ok = panel_lu_solve(A, lda, S, L.lu_nb, xs, lds + L.off_pow);
-      __syncthreads();
     } else {
-      ok = block_lu_solve(A, lda, S, xs, &s_piv);
-      __syncthreads();
+      // the blocked LU is compiled into the 3+1D kernels only (2+1D systems
+      // stay in LDS in the workloads here, and the extra registers would
+      // halve the occupancy of the 2+1D kernels)
+      bool done = false;
+      if constexpr (NS == 3) {
+        if (!L.A_in_lds && L.lu_nb > 0) {
+          ok = panel_lu_solve(A, lda, S, L.lu_nb, xs, lds + L.off_pow);
+          __syncthreads();
+          done = true;
+        }
+      }
+      if (!done) {
+        ok = block_lu_solve(A, lda, S, xs, &s_piv);
+        __syncthreads();
+      }
     }
     if (!ok) {
       if (tid == 0) atomicOr(P.status, kStatSingular);
