@@ -24,7 +24,11 @@ TOL = 1e-10
 # backward-stable solve in another summation order (the matrix-core Gram sums
 # thousands of products per entry) is expected to differ by tens of ulps of
 # backward error: tolerance 50x the one-ulp floor.
-TOL_CASE = {"3d_p8_b_multipass_gram": 1e-9}
+# The same rule at the largest degree with tables (p = 10): the oracle's one-ulp
+# floor is 2.1e-11 .. 6.1e-11 in 1D (condition numbers up to 1.1e14) and
+# 6.9e-10 .. 8.5e-10 in 2D (up to 1.8e19) over three random perturbations, so
+# the tolerances are 50x the largest floor.
+TOL_CASE = {"3d_p8_b_multipass_gram": 1e-9, "1d_p10_max_degree": 3e-9, "2d_p10_max_degree": 4e-8}
 
 
 def say(*a):
@@ -45,6 +49,9 @@ CASES = {
     "3d_p5_b": lambda: (C.cfg5_cube_3d(m=2, p=5, variant="b"), None, None),
     "3d_p3_a_8groups_global_system": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="a", regions=2), None, None),
     "3d_p8_b_multipass_gram": lambda: (C.cfg5_cube_3d(m=2, p=8, variant="b"), None, None),
+    # the largest degree with tables (p = 10)
+    "1d_p10_max_degree": lambda: (C.cfg1_standing_1d(n_elems=8, p=10), None, None),
+    "2d_p10_max_degree": lambda: (C.cfg2_plane_2d(m=3, p=10, T=0.2), None, None),
     # the L-shaped domain of Sec. 6.6 with the corner Bessel data, uniform and graded
     "2d_lshape_uniform_p3": lambda: (C.lshape_2d(0.5, False, T=0.5), None, None),
     "2d_lshape_graded_p3": lambda: (C.lshape_2d(0.4, True, T=0.2), None, None),
