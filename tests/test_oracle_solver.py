@@ -172,3 +172,36 @@ def test_error_functional_closed_form():
     X = o.quad_points()
     e_abs, _ = o.error(pr.data.v(X, 0.37), pr.data.sigma(X, 0.37))
     assert abs(e_abs - np.pi / np.sqrt(2.0)) < 1e-12
+
+
+@pytest.mark.parametrize("name,builder,tol", [
+    ("1d_p10_max_degree", lambda: C.cfg1_standing_1d(n_elems=8, p=10), 3e-9),
+    ("2d_p10_max_degree", lambda: C.cfg2_plane_2d(m=3, p=10, T=0.2), 4e-8),
+])
+def test_parity_tolerance_is_fifty_times_the_one_ulp_floor(name, builder, tol, monkeypatch):
+    """The GPU parity tolerance of the high-degree cases is derived from the
+    oracle itself: its solution moves by its one-ulp floor when every tent
+    matrix and right-hand side is perturbed by a random relative one ulp; the
+    tolerance is 50x the largest floor over three perturbations."""
+    import oracle.tdg as OT
+    from helpers import oracle_for, rel_l2
+
+    pr = builder()
+    o = oracle_for(pr)
+    o.run()
+    ref = np.concatenate([o.v.ravel(), o.sig.ravel()])
+    solve = np.linalg.solve
+    floors = []
+    for seed in (1, 2, 3):
+        rng = np.random.default_rng(seed)
+
+        def noisy(A, b):
+            return solve(A * (1 + rng.uniform(-1, 1, A.shape) * 2.2e-16), b * (1 + rng.uniform(-1, 1, b.shape) * 2.2e-16))
+
+        monkeypatch.setattr(OT.np.linalg, "solve", noisy)
+        o2 = oracle_for(pr)
+        o2.run()
+        monkeypatch.setattr(OT.np.linalg, "solve", solve)
+        floors.append(rel_l2(np.concatenate([o2.v.ravel(), o2.sig.ravel()]), ref))
+    assert max(floors) > 0
+    assert tol / 3 <= 50 * max(floors) <= tol * 1.5, (name, floors)
