@@ -17,7 +17,7 @@ Use.  Per layer the library computes the features, evaluates the network and
 gives each tent the smallest degree whose predicted log indicator is below
 log_eta_tol (else p_max); a tent whose realised indicator exceeds eta_tol is
 solved again one degree higher (up to p_max, where it is accepted) before
-anything is written, so fixed-p_max is both the fallback and the judge.
+anything is written, so fixed p_max is both the fallback and the yardstick.
 """
 from __future__ import annotations
 
