@@ -112,3 +112,27 @@ def test_errors_are_reported_not_raised_across_the_abi():
         with pytest.raises(tdg.TdgError) as ei:
             tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p, bind=False)
         assert ei.value.name == "TDG_EINVAL"
+
+
+def test_gram_modes_and_shapes_are_planned_on_the_host():
+    """The LDS plan is made on the host: both Gram modes fit the 160 KB of a
+    compute unit for the workloads (3+1D p = 8 included), the moment Gram is
+    refused in a mixed-precision context and unknown modes are rejected."""
+    from paper_1907_02367_amd import tdg
+
+    for pr, gamma in ((C.cfg2_plane_2d(m=8), None), (C.cfg5_cube_3d(m=3, p=8, variant="b"), 0.4 * 0.8 ** 2),
+                      (C.lshape_2d(0.3, True, T=0.1), None)):
+        T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, gamma or pr.gamma)
+        ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=pr.p, bind=False)
+        for mode in (0, 1):
+            ctx.set_gram_mode(mode)
+            assert ctx.get_gram_mode() == mode
+            sh = ctx.get_tuning()
+            assert 0 < sh["lds_bytes"] <= 160 * 1024
+        with pytest.raises(tdg.TdgError) as ei:
+            ctx.set_gram_mode(2)
+        assert ei.value.name == "TDG_EINVAL"
+        mixed = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=pr.p, precision=1, bind=False)
+        with pytest.raises(tdg.TdgError) as ei:
+            mixed.set_gram_mode(1)
+        assert ei.value.name == "TDG_EINVAL"
