@@ -37,3 +37,14 @@ def rel_l2(a, b):
     a = np.asarray(a).ravel()
     b = np.asarray(b).ravel()
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def elem_max_rel(a, b):
+    """Largest per-element difference relative to the typical element: max over
+    elements e of ||a_e - b_e|| / (||b|| / sqrt(ne)), arrays (ne, ...).  One
+    element off by d (relative to its own size) shows up as ~d here, where the
+    global relative L2 difference would dilute it by sqrt(ne)."""
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    scale = max(np.linalg.norm(b) / np.sqrt(len(b)), 1e-300)
+    return float(np.linalg.norm(a - b, axis=1).max() / scale)

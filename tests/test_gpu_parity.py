@@ -12,7 +12,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_for, oracle_for, rel_l2
+from helpers import elem_max_rel, gpu_for, oracle_for, rel_l2
 from workloads import configs as C
 from workloads import fields as F
 
@@ -73,9 +73,15 @@ def test_full_run_matches_oracle(name, gram_mode):
     ctx.status()
     r_vs = rel_l2(np.concatenate([v.ravel(), s.ravel()]), np.concatenate([o.v.ravel(), o.sig.ravel()]))
     r_U = rel_l2(U, o.U)
-    say(f"  rel diff (v, sigma) {r_vs:.2e}, U {r_U:.2e}")
+    # per element: no single element may carry a difference the global norm hides
+    # (v and sigma together, as in the global norm: either alone may vanish, e.g.
+    # v of the 1+1D standing wave at T = 1)
+    m_vs = elem_max_rel(np.concatenate([v[..., None], s], -1), np.concatenate([o.v[..., None], o.sig], -1))
+    m_U = elem_max_rel(U, o.U)
+    say(f"  rel diff (v, sigma) {r_vs:.2e}, U {r_U:.2e}; largest per element {m_vs:.2e}, {m_U:.2e}")
     tol = TOL_CASE.get(name, TOL)
     assert r_vs <= tol and r_U <= tol, (r_vs, r_U)
+    assert m_vs <= 10 * tol and m_U <= 10 * tol, (m_vs, m_U)
     if pr.exact:
         f = field or pr.data
         X = o.quad_points()
@@ -287,6 +293,10 @@ MIXED_CASES = {
     "2d_p6_m6": lambda: (C.cfg2_plane_2d(m=6, p=6), None),
     "2d_interface_p3": lambda: (C.cfg4_interface_2d(m=9, p=3), None),
     "3d_p3_b": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="b"), None),
+    # degrees where the FP32 Gram is too ill-conditioned for refinement on most
+    # tents: the per-tent FP64 fallback carries them
+    "2d_p7_m4_fallback": lambda: (C.cfg2_plane_2d(m=4, p=7), None),
+    "2d_p8_m4_fallback": lambda: (C.cfg2_plane_2d(m=4, p=8), None),
 }
 
 
@@ -309,7 +319,11 @@ def test_mixed_precision_matches_oracle(name):
     steps = (ir % 1000)
     r_vs = rel_l2(np.concatenate([v.ravel(), s.ravel()]), np.concatenate([o.v.ravel(), o.sig.ravel()]))
     r_U = rel_l2(U, o.U)
-    say(f"  rel diff (v, sigma) {r_vs:.2e}, U {r_U:.2e}; refinement steps mean {steps.mean():.2f}, "
-        f"FP64 fallback {100 * fb:.1f} %")
+    m_vs = elem_max_rel(np.concatenate([v[..., None], s], -1), np.concatenate([o.v[..., None], o.sig], -1))
+    say(f"  rel diff (v, sigma) {r_vs:.2e}, U {r_U:.2e}, per element {m_vs:.2e}; refinement steps mean "
+        f"{steps.mean():.2f}, FP64 fallback {100 * fb:.1f} %")
     assert (steps >= 1).all()
     assert r_vs <= TOL and r_U <= TOL, (r_vs, r_U)
+    assert m_vs <= 10 * TOL, m_vs
+    if "fallback" in name:
+        assert fb > 0, fb

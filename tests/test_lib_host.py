@@ -112,6 +112,13 @@ def test_errors_are_reported_not_raised_across_the_abi():
         with pytest.raises(tdg.TdgError) as ei:
             tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p, bind=False)
         assert ei.value.name == "TDG_EINVAL"
+    # recovery of U: only the documented values are accepted
+    for ru in (-1, 3, 7):
+        with pytest.raises(tdg.TdgError) as ei:
+            tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, recover_U=ru, bind=False)
+        assert ei.value.name == "TDG_EINVAL"
+    for ru in (0, 1):
+        tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, recover_U=ru, bind=False)
 
 
 def test_gram_modes_and_shapes_are_planned_on_the_host():

@@ -110,3 +110,70 @@ def test_tent_features_closed_form_2d():
     assert f[6] < np.log(1e-25)
     on_bnd = np.any(np.isclose(coords[V], 0.0) | np.isclose(coords[V], 1.0))
     assert f[7] == (1.0 if on_bnd else 0.0)
+
+
+def _patch_measures(coords, elems, P):
+    """|e|, centroid and the covariance of the uniform distribution on each
+    patch element, from the vertices alone (see test_oracle_energy)."""
+    n = coords.shape[1]
+    X = coords[elems[P]]
+    E = X[:, 1:, :] - X[:, :1, :]
+    meas = np.abs(np.linalg.det(E)) / float(np.prod(np.arange(1, n + 1)))
+    xbar = X.mean(axis=1)
+    D = X - xbar[:, None, :]
+    return meas, xbar, np.einsum("eid,eif->edf", D, D) / ((n + 1) * (n + 2))
+
+
+def _interface_oracle():
+    from workloads import configs as C
+
+    pr = C.cfg4_interface_2d(m=7, p=2)
+    tents, lp = pitch(pr.coords, pr.elems, pr.c, 0.2, pr.gamma)
+    o = OracleTDG(pr.coords, pr.elems, pr.c, tents, lp, p=2, q=2)
+    # a vertex on the interface x = 1/2 (both speeds in its patch), not on the boundary
+    V = next(v for v in range(len(pr.coords)) if abs(pr.coords[v, 0] - 0.5) < 1e-12
+             and 0.2 < pr.coords[v, 1] < 0.8)
+    return pr, o, V
+
+
+def test_tent_features_linear_field_spread_and_two_speeds():
+    """Feature 6 (spread about the element means) for v = a.x + b, sigma = s:
+    per element int |v/c - mean|^2 = |e| a^T Cov_e a / c^2, sigma has no
+    spread; feature 4 = log(c_max / c_min) on an interface patch."""
+    pr, o, V = _interface_oracle()
+    X = o.quad_points()
+    a, b, s = np.array([0.9, -1.3]), 0.4, np.array([0.2, 0.5])
+    o.set_initial(X @ a + b, np.broadcast_to(s, X.shape).copy(), None)
+    tb, tt = 0.0, 0.01
+    f = M.tent_features(o, V, tb, tt)
+    P = o.topo.patch[V]
+    c = np.asarray(pr.c)[P]
+    meas, xbar, cov = _patch_measures(pr.coords, pr.elems, P)
+    var = np.einsum("d,edf,f->e", a, cov, a)
+    spread = np.sum(meas * var / c ** 2)
+    norm = np.sum(meas * (((xbar @ a + b) ** 2 + var) / c ** 2 + s @ s))
+    assert np.isclose(f[6], np.log(spread / norm), rtol=0, atol=1e-12)
+    assert set(np.round(c, 12)) == {1.0, 3.0}
+    assert np.isclose(f[3], np.log(3.0)) and np.isclose(f[4], np.log(3.0))
+    assert f[7] == 0.0
+
+
+def test_tent_features_incoming_energy_on_a_tilted_front():
+    """Feature 5 = log(E_bot / |patch|) with the flux form of the energy on a
+    tilted front: constant (v, sigma), grad phi = k on every element, so
+    E_bot = 1/2 sum_e |e| (v^2 / c_e^2 + |s|^2 - 2 v s.k)."""
+    pr, o, V = _interface_oracle()
+    X = o.quad_points()
+    v0, s = 0.7, np.array([-0.6, 0.25])
+    o.set_initial(np.full(X.shape[:2], v0), np.broadcast_to(s, X.shape).copy(), None)
+    k = np.array([0.2, -0.15])
+    o.tau[:] = pr.coords @ k + 0.3
+    tb = o.tau[V]
+    f = M.tent_features(o, V, tb, tb + 0.01)
+    P = o.topo.patch[V]
+    c = np.asarray(pr.c)[P]
+    meas, _, _ = _patch_measures(pr.coords, pr.elems, P)
+    E = 0.5 * np.sum(meas * (v0 ** 2 / c ** 2 + s @ s - 2.0 * v0 * (s @ k)))
+    assert np.isclose(f[5], np.log(E / meas.sum()), rtol=0, atol=1e-12)
+    # constant values: no spread
+    assert f[6] < np.log(1e-25)
