@@ -96,7 +96,8 @@ typedef struct {
   double beta;       /* interface penalty (Sec. 2.4), e.g. 0.5 */
   int32_t precision; /* 0 = FP64; 1 = FP32 matrix-core Gram + FP64 LU + FP64 refinement */
   int32_t layout;    /* must be 1: values stored at spatial quadrature points (Sec. 4.1) */
-  int32_t recover_U; /* 1: one mean-matching row per speed group recovers U (Sec. 5); 0: off */
+  int32_t recover_U; /* 1: one mean-matching row per speed group recovers U (Sec. 5); 0: off;
+                        any other value: TDG_EINVAL */
 } tdg_opts;
 
 enum {
@@ -165,7 +166,9 @@ int trefftz_table_info(const tdg_ctx* ctx, int32_t p, int32_t* N, int32_t* nnz_f
  * LDS, else 4, 8, 16, 32 or 64 if it fits); persistent = 1: a grid of resident
  * workgroups takes the layer's tents from a device counter (balances tents of
  * uneven size and degree), 0: one workgroup per tent.  Results do not depend
- * on the shape.  TDG_EINVAL if the shape does not fit. */
+ * on the shape.  TDG_EINVAL if the shape does not fit.  A sweep recorded by
+ * trefftz_capture_sweep is released (it holds the old shape): replay then
+ * returns TDG_ESTATE until the next capture. */
 int trefftz_set_tuning(tdg_ctx* ctx, int32_t pts_per_chunk, int32_t persistent);
 /* How the top Gram, the bottom right-hand side, the recovery row and the
  * Dirichlet terms of eq. 4.1 are formed (FP64 contexts):
@@ -175,7 +178,8 @@ int trefftz_set_tuning(tdg_ctx* ctx, int32_t pts_per_chunk, int32_t persistent);
  *     the sparse field tables (work ~ points x (monomials of degree <= 2p-2)
  *     + the table terms), far less at high degree.
  * Both give the same system up to rounding.  TDG_EINVAL for mode 1 in a
- * mixed-precision context or if it does not fit in LDS. */
+ * mixed-precision context or if it does not fit in LDS.  Like
+ * trefftz_set_tuning, a successful call releases a recorded sweep. */
 int trefftz_set_gram_mode(tdg_ctx* ctx, int32_t mode);
 int trefftz_get_gram_mode(const tdg_ctx* ctx, int32_t* mode);
 int trefftz_get_tuning(const tdg_ctx* ctx, int32_t* pts_per_chunk, int32_t* persistent, int32_t* lds_bytes);

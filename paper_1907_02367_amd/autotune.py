@@ -5,8 +5,10 @@ per tent); it changes speed, not results beyond rounding.  Each feasible shape
 is timed with HIP events on the first layers of the sweep (from the initial
 state), the fastest is kept, and the choice is cached in a JSON file keyed by
 the problem class (dimension, degree, speed groups, mesh size, tents per
-layer).  Gram modes: 0 = basis values at the points on the matrix cores,
-1 = monomial moments (FP64 contexts only).
+layer) and by a hash of the kernel sources, so that a shape tuned for an
+earlier kernel is not reused after the kernel changes.  Gram modes: 0 = basis
+values at the points on the matrix cores, 1 = monomial moments (FP64 contexts
+only).
 """
 from __future__ import annotations
 
@@ -20,10 +22,22 @@ CACHE = os.environ.get("TDG_TUNING_CACHE", os.path.join(os.path.expanduser("~"),
 SHAPES = [(pch, pers) for pch in (64, 32, 16, 8, 4) for pers in (0, 1)]
 
 
+def kernel_source_hash():
+    """First 16 hex digits of the SHA-256 of the tent kernel's sources."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in ("tent_kernel.hip", "tdg_internal.h", "api.cpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def problem_key(ctx, p_max):
     t = ctx.tents
     width = int(np.diff(t.layer_ptr).mean()) if t.n_layers else 0
-    return f"n{ctx.n}_p{p_max}_ne{ctx.ne}_Q{ctx.Q}_w{width}_prec{ctx.precision}"
+    return f"n{ctx.n}_p{p_max}_ne{ctx.ne}_Q{ctx.Q}_w{width}_prec{ctx.precision}_k{kernel_source_hash()}"
 
 
 def _load():

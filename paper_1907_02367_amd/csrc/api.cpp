@@ -354,6 +354,7 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   if (opts->layout != 1) return fail(TDG_EINVAL, "layout must be 1 (values at quadrature points)");
   if (opts->precision != 0 && opts->precision != 1) return fail(TDG_EINVAL, "precision must be 0 or 1");
   if (!(opts->alpha > 0) || !(opts->beta > 0)) return fail(TDG_EINVAL, "alpha and beta must be positive");
+  if (opts->recover_U != 0 && opts->recover_U != 1) return fail(TDG_EINVAL, "recover_U must be 0 or 1");
   auto X = new tdg_ctx();
   std::unique_ptr<tdg_ctx> guard(X);
   std::string err;
@@ -904,6 +905,13 @@ int trefftz_table_info(const tdg_ctx* X, int32_t p, int32_t* N, int32_t* nnz_fie
   return TDG_OK;
 }
 
+static void drop_graph(tdg_ctx* X) {
+  if (X->graph_exec) hipGraphExecDestroy(X->graph_exec);
+  if (X->graph) hipGraphDestroy(X->graph);
+  X->graph_exec = nullptr;
+  X->graph = nullptr;
+}
+
 int trefftz_set_tuning(tdg_ctx* X, int32_t pts_per_chunk, int32_t persistent) {
   if (!X) return fail(TDG_EINVAL, "NULL argument");
   if (persistent != 0 && persistent != 1) return fail(TDG_EINVAL, "persistent must be 0 or 1");
@@ -920,6 +928,9 @@ int trefftz_set_tuning(tdg_ctx* X, int32_t pts_per_chunk, int32_t persistent) {
   }
   X->forced_pch = pts_per_chunk;
   X->persistent = persistent;
+  // a captured sweep holds the old plan (LDS carve-up, kernel) in its kernel
+  // nodes while the descriptors in device memory follow the new one: drop it
+  drop_graph(X);
   if (X->bound) {
     if (upload_tabd(X, nullptr, false)) return fail(TDG_EHIP, "upload of the degree descriptors failed");
     if (set_kernel_smem_limit(X->topo.n, (size_t)X->lp.total * 8 + 64)) return fail(TDG_EHIP, "cannot raise the LDS limit");
@@ -943,6 +954,7 @@ int trefftz_set_gram_mode(tdg_ctx* X, int32_t mode) {
     X->gram_mode = old_mode;
     return rc;
   }
+  drop_graph(X);  // (see trefftz_set_tuning)
   if (X->bound) {
     if (upload_tabd(X, nullptr, false)) return fail(TDG_EHIP, "upload of the degree descriptors failed");
     if (set_kernel_smem_limit(X->topo.n, (size_t)X->lp.total * 8 + 64)) return fail(TDG_EHIP, "cannot raise the LDS limit");
@@ -963,13 +975,6 @@ int trefftz_get_tuning(const tdg_ctx* X, int32_t* pts_per_chunk, int32_t* persis
   if (persistent) *persistent = X->persistent;
   if (lds_bytes) *lds_bytes = X->lp.total * 8;
   return TDG_OK;
-}
-
-static void drop_graph(tdg_ctx* X) {
-  if (X->graph_exec) hipGraphExecDestroy(X->graph_exec);
-  if (X->graph) hipGraphDestroy(X->graph);
-  X->graph_exec = nullptr;
-  X->graph = nullptr;
 }
 
 int trefftz_capture_sweep(tdg_ctx* X, int32_t layer_begin, int32_t layer_end, const int8_t* p_per_tent,

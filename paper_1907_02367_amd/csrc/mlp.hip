@@ -5,8 +5,9 @@
 // p = 2..8, eta_T being the energy of the jump between the tent solution of
 // degree p and the incoming trace on the bottom facets (computed by the tent
 // kernel).  The degree used is the smallest p whose prediction is below
-// log(eta_tol); the tent kernel re-solves at p_max if the realised indicator
-// exceeds eta_tol.
+// log(eta_tol); a tent whose realised indicator exceeds eta_tol is solved
+// again by the tent kernel one degree higher, step by step up to p_max, where
+// it is accepted.
 //
 // Parameter vector (kNParam floats / BF16 values):
 //   W1[kHid][kFeat], b1[kHid], W2[kHid][kHid], b2[kHid], W3[kOut][kHid], b3[kOut]
