@@ -249,6 +249,17 @@ int tdg_mlp_forward(const uint16_t* w_bf16, const float* x, int64_t n, float* y,
  * in block order (deterministic). */
 int tdg_mlp_backward(const uint16_t* w_bf16, const float* x, const float* target, const float* mask, int64_t n,
                      float norm, float* partial, float* grad, tdg_stream stream);
+/* The same gradient for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * per-block partial gradients live in a fixed device array of the library
+ * (one per GPU, 256 blocks x (nparam+1) floats = 5.3 MB, held until the
+ * process ends) instead of a caller scratch, and the call allocates nothing.
+ * Same kernels and summation order as tdg_mlp_backward, so the same result.
+ * 1 <= n <= 8192 samples (TDG_EINVAL beyond, with a message).  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (streams
+ * running concurrently) race and must be ordered by the caller. */
+int tdg_mlp_backward_noalloc(const uint16_t* w_bf16, const float* x, const float* target, const float* mask,
+                             int64_t n, float norm, float* grad, tdg_stream stream);
 /* One Adam step (Kingma and Ba) on the FP32 master weights w32 with moments
  * m, v (step >= 1 counts from 1), then w_bf16 = round-to-nearest-even(w32). */
 int tdg_mlp_adam(float* w32, uint16_t* w_bf16, const float* grad, float* m, float* v, int32_t step, float lr,

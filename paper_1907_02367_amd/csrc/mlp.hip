@@ -14,6 +14,8 @@
 // Activation: tanh.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "tdg_internal.h"
 
 namespace tdg {
@@ -158,6 +160,14 @@ __global__ void mlp_reduce_kernel(const float* partial, int nblocks, float* grad
   for (int b = 0; b < nblocks; ++b) g += partial[(long long)b * (kNParam + 1) + i];
   grad[i] = g;
 }
+
+// Fixed scratch of tdg_mlp_backward_noalloc: the per-block partial gradients of
+// at most kNoAllocMaxSamples samples.  Each GPU the library runs on holds its
+// own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr long long kNoAllocMaxBlocks = kNoAllocMaxSamples / kMBB;
+static_assert(kNoAllocMaxSamples % kMBB == 0, "whole blocks");
+__device__ __align__(256) float scratch[kNoAllocMaxBlocks * (kNParam + 1)];
 
 __global__ void mlp_adam_kernel(float* w32, unsigned short* wb, const float* grad, float* m, float* v, int step, float lr,
                                 float b1, float b2, float eps) {
@@ -320,6 +330,34 @@ int launch_select(const unsigned short* wb, const float* feats, int t0, int coun
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept; each GPU holds its own copy at its own
+// address.  The array's name is only a host-side stand-in and is never passed
+// to a kernel or a copy.
+int noalloc_scratch(float** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static float* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_error(std::string("tdg_mlp_backward_noalloc: no usable current device: ") + hipGetErrorString(e));
+    return TDG_EHIP;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("tdg_mlp_backward_noalloc: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+      return TDG_EHIP;
+    }
+    addr[dev] = static_cast<float*>(p);
+  }
+  *out = addr[dev];
+  return TDG_OK;
+}
+
 }  // namespace tdg
 
 // ---- C-ABI of the degree network ----------------------------------------------------
@@ -345,6 +383,31 @@ int tdg_mlp_backward(const uint16_t* w_bf16, const float* x, const float* target
     tdg::set_error("tdg_mlp_backward: NULL pointer, n < 1 or norm <= 0");
     return TDG_EINVAL;
   }
+  const long long nb = (n + tdg::kMBB - 1) / tdg::kMBB;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(tdg::mlp_backward_kernel, dim3((unsigned)nb), dim3(tdg::kMBB), 0, s,
+                     (const unsigned short*)w_bf16, x, target, mask, (long long)n, norm, partial);
+  hipLaunchKernelGGL(tdg::mlp_reduce_kernel, dim3((tdg::kNParam + 1 + 255) / 256), dim3(256), 0, s, partial, (int)nb,
+                     grad);
+  return hipGetLastError() == hipSuccess ? TDG_OK : TDG_EHIP;
+}
+
+int tdg_mlp_backward_noalloc(const uint16_t* w_bf16, const float* x, const float* target, const float* mask,
+                             int64_t n, float norm, float* grad, tdg_stream stream) {
+  if (!w_bf16 || !x || !target || !mask || !grad || n <= 0 || !(norm > 0)) {
+    tdg::set_error("tdg_mlp_backward_noalloc: NULL pointer, n < 1 or norm <= 0");
+    return TDG_EINVAL;
+  }
+  if (n > tdg::kNoAllocMaxSamples) {
+    tdg::set_error("tdg_mlp_backward_noalloc: n = " + std::to_string((long long)n) + " exceeds the fixed scratch (" +
+                   std::to_string(tdg::kNoAllocMaxSamples) + " samples)");
+    return TDG_EINVAL;
+  }
+  float* partial = nullptr;
+  const int rc = tdg::noalloc_scratch(&partial);
+  if (rc != TDG_OK) return rc;
+  // every block writes its whole row of partial (kNParam + 1 floats) and the
+  // reduction reads only the rows of this call, so nothing needs clearing
   const long long nb = (n + tdg::kMBB - 1) / tdg::kMBB;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(tdg::mlp_backward_kernel, dim3((unsigned)nb), dim3(tdg::kMBB), 0, s,

@@ -26,6 +26,9 @@ constexpr int kFeat = 8;
 constexpr int kHid = 64;
 constexpr int kOut = 7;
 constexpr int kNParam = kHid * kFeat + kHid + kHid * kHid + kHid + kOut * kHid + kOut;
+// samples one call of the allocation-free network gradient can take (its fixed
+// device scratch holds the partial gradients of kNoAllocMaxSamples / 32 blocks)
+constexpr long long kNoAllocMaxSamples = 8192;
 
 // Sparse tables of the Trefftz basis of U^p (c = 1) over the monomials
 // t^k x^alpha, k + |alpha| <= p, ordered by total degree, so the first M1
@@ -158,6 +161,7 @@ int launch_features(const KParams& P, int t0, int count, float* feats, void* str
 int launch_select(const unsigned short* wb, const float* feats, int t0, int count, float log_tol, int pmax,
                   signed char* p_sel, void* stream);
 int launch_norms(const KParams& P, int kind, const double* ex, double* partial, int nblocks, double* out, void* stream);
+int noalloc_scratch(float** out);  // device address of the fixed network-gradient scratch (current device)
 
 // ---- host-side components ----------------------------------------------------
 struct Topology {

@@ -85,6 +85,8 @@ EXPORTS = {
     "tdg_mlp_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p],
     "tdg_mlp_backward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                          ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "tdg_mlp_backward_noalloc": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p],
     "tdg_mlp_adam": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                      ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_void_p],
     "tdg_mlp_round": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
@@ -174,6 +176,16 @@ def mlp_backward(w_bf16, x, target, mask, norm, partial=None, grad=None, stream=
                                   ctypes.c_void_p(partial.data_ptr()), _dptr(grad, "float32", (P + 1,)),
                                   _stream(stream)))
     return grad, partial
+
+
+def mlp_backward_noalloc(w_bf16, x, target, mask, norm, grad, stream=None):
+    """tdg_mlp_backward_noalloc: the gradient into the caller's grad (nparam+1
+    float32) with the library's fixed scratch (n <= 8192 samples)."""
+    n, P = x.shape[0], mlp_nparam()
+    _check(lib().tdg_mlp_backward_noalloc(_dptr(w_bf16, "int16", (P,)), _dptr(x, "float32", (n, 8)),
+                                          _dptr(target, "float32", (n, 7)), _dptr(mask, "float32", (n, 7)), n,
+                                          float(norm), _dptr(grad, "float32", (P + 1,)), _stream(stream)))
+    return grad
 
 
 def mlp_adam(w32, w_bf16, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, stream=None):
