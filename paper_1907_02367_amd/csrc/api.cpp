@@ -59,7 +59,7 @@ struct tdg_ctx {
   std::vector<int> hi32;
   struct TabOff {
     size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx, ue_ptr, ue_idx, tr_ptr, tr_j, expo2, K2, task2,
-        task1;  // i32
+        task1, mt_ex, mt_map;  // i32
     size_t ue_coef, tr_coef;                                                           // f64
     size_t fo_coef, u_coef, fo_coef32;                 // f64 (fo_coef32: floats packed two per double)
   } toff[kMaxP + 1];
@@ -459,6 +459,8 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     o.K2 = push(X->hi32, tb.K2.data(), tb.K2.size());
     o.task2 = push(X->hi32, tb.task2.data(), tb.task2.size());
     o.task1 = push(X->hi32, tb.task1.data(), tb.task1.size());
+    o.mt_ex = push(X->hi32, tb.mt_ex.data(), tb.mt_ex.size());
+    o.mt_map = push(X->hi32, tb.mt_map.data(), tb.mt_map.size());
     o.ue_coef = push(X->hf64, tb.ue_coef.data(), tb.ue_coef.size());
     o.tr_coef = push(X->hf64, tb.tr_coef.data(), tb.tr_coef.size());
     o.fo_coef = push(X->hf64, tb.fo_coef.data(), tb.fo_coef.size());
@@ -620,6 +622,9 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
     D.task1 = I + o.task1;
     D.ntask2 = tb.ntask2;
     D.ntask1 = tb.ntask1;
+    D.mt_ntile = tb.mt_ntile;
+    D.mt_ex = I + o.mt_ex;
+    D.mt_map = I + o.mt_map;
     D.fo_nnz = (int)tb.fo_idx.size();
     D.u_nnz = (int)tb.u_idx.size();
     D.ue_n = tb.ue_ptr.back();
@@ -1022,6 +1027,27 @@ int trefftz_tent_stats(tdg_ctx* X, int64_t first_tent, int64_t count, int32_t* i
   if (dissipation && count)
     HIP_OK(hipMemcpyAsync(dissipation, X->kp.dissip + first_tent, count * 8, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  return TDG_OK;
+}
+
+// Internal (not part of include/tdg.h): the moment tables of degree p and the
+// current LDS plan, host copies, for the host-side replay of the kernel's index
+// arithmetic in the tests.  info[16] = {M, M1, M2, ntask2, ntask1, mt_ntile, Q,
+// pch[p], off_pt, off_pow, off_W1, off_fg, total, moment, n, pmax}; each array
+// (nullable) receives the table as built (task words, mt_ex, mt_map).
+int tdg_debug_moment_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t* task2, int32_t* task1,
+                            int32_t* mt_ex, int32_t* mt_map) {
+  if (!X || !info) return fail(TDG_EINVAL, "NULL argument");
+  if (p < 1 || p > X->opts.p_max) return fail(TDG_EINVAL, "p out of range");
+  const Table& t = X->tabs[p];
+  const LdsPlan& L = X->lp;
+  const int32_t v[16] = {t.M, t.M1, t.M2, t.ntask2, t.ntask1, t.mt_ntile, X->quad.Q, L.pch[p], L.off_pt,
+                         L.off_pow, L.off_W1, L.off_fg, L.total, L.moment, X->topo.n, X->opts.p_max};
+  std::copy(v, v + 16, info);
+  if (task2) std::copy(t.task2.begin(), t.task2.end(), task2);
+  if (task1) std::copy(t.task1.begin(), t.task1.end(), task1);
+  if (mt_ex) std::copy(t.mt_ex.begin(), t.mt_ex.end(), mt_ex);
+  if (mt_map) std::copy(t.mt_map.begin(), t.mt_map.end(), mt_map);
   return TDG_OK;
 }
 

@@ -17,6 +17,11 @@ constexpr int kMaxP = 10;        // highest degree of U^p with tables
 constexpr int kTaskInts = 3;
 constexpr int kTaskSlots = 6;   // moment-monomial tasks per thread held in registers (<= kTaskSlots * kBlock)
 constexpr int kTaskSlots1 = 2;  // tasks over the monomials of degree <= p, per thread
+// Top moments on the FP64 matrix cores (3+1D moment Gram): the moment monomial
+// t^k x1^a1 x2^a2 x3^a3 is L(t, x1) R(x2, x3); over the points of one element
+// the moments of all products form the 16x16 tiles of (w L)^T R, only the tiles
+// with a product of degree <= 2p-2 are formed, at most kMomTileSlots per wave
+constexpr int kMomTileSlots = 6;
 constexpr int kMaxGroups = 8;    // speed groups inside one tent (Sec. 4.2)
 constexpr int kMaxPatch = 64;    // elements in one vertex patch
 constexpr int kMaxFaces = 64;    // Dirichlet facets containing one vertex
@@ -45,6 +50,13 @@ struct TableDesc {
   const int* task2;  // ntask2 moment tasks over the moment monomials (degree <= 2p-2)
   const int* task1;  // ntask1 moment tasks over the monomials of degree <= p
   int ntask2, ntask1;
+  // matrix-core top moments (3+1D): mt_ntile tiles (0: not used at this degree);
+  // per tile and lane l%16 the packed exponents a0 | a1 << 5 (row 16 I + l%16 of
+  // the L list) | c0 << 10 | c1 << 15 (column 16 J + l%16 of the R list):
+  // mt_ex[tile*16 + l%16]; mt_map[tile*256 + row*16 + col] = moment index or -1
+  int mt_ntile;
+  const int* mt_ex;
+  const int* mt_map;
   // entry form: entries of basis function j+1 are ue_ptr[j]..ue_ptr[j+1]-1; entry e
   // holds (n+2) pairs (monomial index, coefficient) for U, v = dU/dt and
   // sigma_m = -dU/dx_m: ue_idx[e*(n+2)+s], ue_coef[e*(n+2)+s] (coefficient 0 if absent)
@@ -194,6 +206,8 @@ struct Table {
   std::vector<int> K2;     // M1*M1: index in expo2 of the product of monomials k and l
   std::vector<int> task2, task1;  // moment tasks (kTaskInts ints each) over expo2 and over expo
   int ntask2 = 0, ntask1 = 0;
+  int mt_ntile = 0;                // matrix-core top-moment tiles (see TableDesc)
+  std::vector<int> mt_ex, mt_map;
   std::vector<int> parent, var;
   std::vector<int> expo;  // M*(n+1): k, alpha_1..alpha_n
   std::vector<int> fo_ptr, fo_idx;

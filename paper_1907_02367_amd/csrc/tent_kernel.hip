@@ -740,6 +740,194 @@ __device__ inline void moment_points(const double* lam_ref, const double* w_ref,
 }
 
 
+// Moments over the points of one speed group (3+1D), element by element, with
+// the top moments on the FP64 matrix cores.  A moment monomial factors as
+// m_b = L_i(th, xh_1) R_j(xh_2, xh_3); over the points of one element the
+// moments of all products are the tiles of C_e = (w L)^T R, a 16x16x4 MFMA
+// per tile and four points (lane l: row or column l%16, point l/16 of the
+// step).  grad phi_new is constant on an element, so after its last chunk
+//   nu[b] += C_e[b],  nu_d[b] += g_d C_e[b]   (b = mt_map of the tile entry)
+// and the tiles restart from zero.  The bottom moments and the recovery-row
+// sums are those of moment_points (VALU tasks).  Chunks hold at most PCH points
+// of one element (PCH a multiple of 4: every k-step reads inside the chunk's
+// regions; points past the chunk enter with zero operands).
+template <int NS>
+__device__ inline void moment_points_mt(const double* lam_ref, const double* w_ref, const double* state, int Q,
+                                        const double* EL, int ELS, const int* gel, int nel, const double* XV,
+                                        double cr, double hr, double tmid, double dt, int p, int PCH, int M1, int M2,
+                                        int Mm, const int* task1, int ntask1, int ntile, const int* mt_ex,
+                                        const int* mt_map, double* NU, double* BV, double* BU, double* PV, double* PW,
+                                        double* PD, double* POWT, double* POWB, double* A00r, double* r0r) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int E2 = 2 * p - 1;
+  const double ic2 = 1.0 / (cr * cr);
+  for (int i = tid; i < (NS + 1) * M2 + (NS + 1) * M1 + Mm; i += blockDim.x) NU[i] = 0.0;
+  double sw_acc = 0.0, su_acc = 0.0;
+  TaskRegs<kTaskSlots1> RB;
+  load_tasks(task1, ntask1, RB);
+  unsigned tex[kMomTileSlots];
+  d4 acc[kMomTileSlots];
+#pragma unroll
+  for (int s = 0; s < kMomTileSlots; ++s) {
+    const int t = wave + 4 * s;
+    tex[s] = t < ntile ? (unsigned)mt_ex[t * 16 + (lane & 15)] : 0u;
+    acc[s] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  __syncthreads();
+  for (int ei = 0; ei < nel; ++ei) {
+    const double* R = EL + gel[ei] * ELS;
+    for (int q0 = 0; q0 < Q; q0 += PCH) {
+      const int nc = min(PCH, Q - q0);
+      for (int pt = tid; pt < nc; pt += blockDim.x) {
+        const int q = q0 + pt;
+        const int lV = (int)R[El<NS>::LV];
+        const int e = (int)R[El<NS>::E];
+        const double* lam = lam_ref + (size_t)q * (NS + 1);
+        double xt[NS], pho = 0.0;
+        for (int d = 0; d < NS; ++d) xt[d] = 0.0;
+        for (int k = 0; k <= NS; ++k) {
+          pho += lam[k] * R[El<NS>::TAU + k];
+          for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
+        }
+        const double phi = pho + lam[lV] * dt;
+        const double w = w_ref[q] * R[El<NS>::DET];
+        const double* st = state + (size_t)e * (NS + 2) * Q;
+        const double vb = st[q];
+        double sg = 0.0;
+        for (int d = 0; d < NS; ++d) sg += st[(1 + d) * Q + q] * R[El<NS>::GOLD + d];
+        PD[pt * (NS + 2)] = w * (ic2 * vb - sg);
+        for (int d = 0; d < NS; ++d) PD[pt * (NS + 2) + 1 + d] = w * (st[(1 + d) * Q + q] - vb * R[El<NS>::GOLD + d]);
+        PD[pt * (NS + 2) + NS + 1] = w * st[(NS + 1) * Q + q];
+        PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
+        PV[(PCH + pt) * (NS + 1)] = cr * (pho - tmid) / hr;
+        for (int d = 0; d < NS; ++d) {
+          const double xh = (xt[d] - XV[d]) / hr;
+          PV[pt * (NS + 1) + 1 + d] = xh;
+          PV[(PCH + pt) * (NS + 1) + 1 + d] = xh;
+        }
+        PW[pt] = w;
+      }
+      __syncthreads();
+      for (int i = tid; i < nc * (NS + 1); i += blockDim.x) {
+        const int pt = i / (NS + 1), v = i % (NS + 1);
+        double x = PV[pt * (NS + 1) + v], a = 1.0;
+        double* o = POWT + (pt * (NS + 1) + v) * E2;
+        for (int ee = 0; ee < E2; ++ee) {
+          o[ee] = a;
+          a *= x;
+        }
+        x = PV[(PCH + pt) * (NS + 1) + v];
+        a = 1.0;
+        o = POWB + (pt * (NS + 1) + v) * (p + 1);
+        for (int ee = 0; ee <= p; ++ee) {
+          o[ee] = a;
+          a *= x;
+        }
+      }
+      __syncthreads();
+      // top moment tiles of this chunk
+      const int nks = (nc + 3) >> 2;
+      for (int ks = 0; ks < nks; ++ks) {
+        const int pt = ks * 4 + (lane >> 4);
+        const bool ok = pt < nc;
+        const double* pw = POWT + pt * (NS + 1) * E2;
+        const double w = ok ? PW[pt] : 0.0;
+#pragma unroll
+        for (int s = 0; s < kMomTileSlots; ++s) {
+          if (wave + 4 * s < ntile) {
+            const unsigned ex = tex[s];
+            double a = 0.0, b = 0.0;
+            if (ok) {
+              a = w * pw[ex & 31u] * pw[E2 + ((ex >> 5) & 31u)];
+              b = pw[2 * E2 + ((ex >> 10) & 31u)] * pw[3 * E2 + ((ex >> 15) & 31u)];
+            }
+            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+          }
+        }
+      }
+      // bottom moments (monomials of degree <= p), VALU tasks
+#pragma unroll
+      for (int sl = 0; sl < kTaskSlots1; ++sl) {
+        if (tid + sl * (int)blockDim.x >= ntask1) break;
+        const unsigned w0 = RB.w0[sl];
+        int e[NS];
+#pragma unroll
+        for (int v = 0; v < NS; ++v) e[v] = task_exp(w0, v);
+        const int d0 = task_exp(w0, 3);
+        double bu[4], bv[4][NS + 1];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          bu[c] = 0.0;
+#pragma unroll
+          for (int q = 0; q <= NS; ++q) bv[c][q] = 0.0;
+        }
+#pragma unroll 1
+        for (int pt = 0; pt < nc; ++pt) {
+          const double* pw = POWB + pt * (NS + 1) * (p + 1);
+          double pre = pw[e[0]];
+#pragma unroll
+          for (int v = 1; v < NS; ++v) pre *= pw[v * (p + 1) + e[v]];
+          const double z = pw[NS * (p + 1) + 1];
+          double mv = pre * pw[NS * (p + 1) + d0];
+          const double w = PW[pt];
+          double dd[NS + 1];
+#pragma unroll
+          for (int q = 0; q <= NS; ++q) dd[q] = PD[pt * (NS + 2) + q];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            bu[c] += w * mv;
+#pragma unroll
+            for (int q = 0; q <= NS; ++q) bv[c][q] += dd[q] * mv;
+            mv *= z;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int k = task_idx(RB, sl, c);
+          if (k < 0) continue;
+          BU[k] += bu[c];
+          if (k < M1)
+#pragma unroll
+            for (int q = 0; q <= NS; ++q) BV[q * M1 + k] += bv[c][q];
+        }
+      }
+      if (tid == blockDim.x - 1)
+        for (int pt = 0; pt < nc; ++pt) {
+          sw_acc += PW[pt];
+          su_acc += PD[pt * (NS + 2) + NS + 1];
+        }
+      __syncthreads();
+    }
+    // fold the element's tiles (each moment index belongs to one tile entry, so
+    // no two lanes or waves write the same word)
+    double g[NS];
+#pragma unroll
+    for (int d = 0; d < NS; ++d) g[d] = R[El<NS>::GNEW + d];
+#pragma unroll
+    for (int s = 0; s < kMomTileSlots; ++s) {
+      const int t = wave + 4 * s;
+      if (t < ntile) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int b = mt_map[t * 256 + ((lane >> 4) + 4 * r) * 16 + (lane & 15)];
+          if (b >= 0) {
+            const double c = acc[s][r];
+            NU[b] += c;
+#pragma unroll
+            for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += g[d] * c;
+          }
+        }
+        acc[s] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == blockDim.x - 1) {
+    *A00r += sw_acc;
+    *r0r += su_acc;
+  }
+}
+
 // Fields of the solution at one point from the monomial runs of the degree-p
 // table: val[c] += sum_k cm[c*M + k] m_k(var) for c <= NS over the monomials of
 // degree <= p-1 (v, sigma), and with WITH_U val[NS+1] over all monomials (U).
@@ -1055,9 +1243,19 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
       const double cr = gc[r], hr = gh[r];
       const double ic2 = 1.0 / (cr * cr);
       const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
-      moment_points<NS>(P.lam_ref, P.w_ref, P.state, Q, EL, ELS, s_gel + s_goff[r], npts, XV, cr, hr, tmid, dt, p,
-                        PCH, M1, M2, Mm, T.task1, T.ntask1, T.task2, T.ntask2, NU, BV, BU, PV, PW, PD, PG, POWT,
-                        POWB, A00 + r, r0 + r);
+      bool done_mt = false;
+      if constexpr (NS == 3) {
+        if (Dp.mt_ntile > 0) {
+          moment_points_mt<NS>(P.lam_ref, P.w_ref, P.state, Q, EL, ELS, s_gel + s_goff[r], s_goff[r + 1] - s_goff[r],
+                               XV, cr, hr, tmid, dt, p, PCH, M1, M2, Mm, T.task1, T.ntask1, Dp.mt_ntile, Dp.mt_ex,
+                               Dp.mt_map, NU, BV, BU, PV, PW, PD, POWT, POWB, A00 + r, r0 + r);
+          done_mt = true;
+        }
+      }
+      if (!done_mt)
+        moment_points<NS>(P.lam_ref, P.w_ref, P.state, Q, EL, ELS, s_gel + s_goff[r], npts, XV, cr, hr, tmid, dt, p,
+                          PCH, M1, M2, Mm, T.task1, T.ntask1, T.task2, T.ntask2, NU, BV, BU, PV, PW, PD, PG, POWT,
+                          POWB, A00 + r, r0 + r);
       // right-hand side and recovery row of group r
       for (int i = tid; i < NW; i += blockDim.x) {
         double b = 0.0;

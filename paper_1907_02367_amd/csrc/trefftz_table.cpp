@@ -289,6 +289,55 @@ Table build_table(int n, int p) {
   };
   tasks(T.expo2, T.M2, T.task2);
   T.ntask2 = (int)(T.task2.size() / kTaskInts);
+  // matrix-core tiles of the top moments (3+1D): L = t^a0 x1^a1 and
+  // R = x2^c0 x3^c1, each list of degree <= D = 2p-2 ordered by degree, so a
+  // 16-row block of L and a 16-column block of R hold a product of degree <= D
+  // only if their smallest degrees add up to at most D; the moment index of
+  // every such product (or -1 past D or past the lists) is tabulated
+  if (n == 3 && p >= 2) {
+    const int D = 2 * p - 2;
+    std::vector<std::array<int, 2>> Ls, Rs;
+    for (int d = 0; d <= D; ++d)
+      for (int a = d; a >= 0; --a) Ls.push_back({a, d - a});
+    Rs = Ls;
+    const int nI = ((int)Ls.size() + 15) / 16, nJ = ((int)Rs.size() + 15) / 16;
+    auto deg = [](const std::array<int, 2>& e) { return e[0] + e[1]; };
+    std::map<Key, int> index2;
+    for (int i = 0; i < T.M2; ++i) {
+      Key k{0, 0, 0, 0};
+      for (int j = 0; j <= n; ++j) k[j] = T.expo2[(size_t)i * (n + 1) + j];
+      index2[k] = i;
+    }
+    std::vector<std::array<int, 2>> tiles;
+    for (int I = 0; I < nI; ++I)
+      for (int J = 0; J < nJ; ++J)
+        if (deg(Ls[16 * I]) + deg(Rs[16 * J]) <= D) tiles.push_back({I, J});
+    if ((int)tiles.size() <= 4 * kMomTileSlots) {
+      T.mt_ntile = (int)tiles.size();
+      std::vector<int> seen((size_t)T.M2, 0);
+      for (auto& tj : tiles) {
+        for (int l = 0; l < 16; ++l) {
+          const int i = 16 * tj[0] + l, j = 16 * tj[1] + l;
+          const std::array<int, 2> a = i < (int)Ls.size() ? Ls[i] : std::array<int, 2>{0, 0};
+          const std::array<int, 2> c = j < (int)Rs.size() ? Rs[j] : std::array<int, 2>{0, 0};
+          T.mt_ex.push_back(a[0] | a[1] << 5 | c[0] << 10 | c[1] << 15);
+        }
+        for (int r = 0; r < 16; ++r)
+          for (int cc = 0; cc < 16; ++cc) {
+            const int i = 16 * tj[0] + r, j = 16 * tj[1] + cc;
+            int b = -1;
+            if (i < (int)Ls.size() && j < (int)Rs.size() && deg(Ls[i]) + deg(Rs[j]) <= D) {
+              b = index2.at(Key{Ls[i][0], Ls[i][1], Rs[j][0], Rs[j][1]});
+              seen[(size_t)b]++;
+            }
+            T.mt_map.push_back(b);
+          }
+      }
+      // every moment monomial is formed exactly once
+      for (int i = 0; i < T.M2; ++i)
+        if (seen[(size_t)i] != 1) throw std::runtime_error("matrix-core moment tiles do not cover the moments");
+    }
+  }
   tasks(T.expo, T.M, T.task1);
   T.ntask1 = (int)(T.task1.size() / kTaskInts);
   // transposed form: rows comp*M + monomial

@@ -1,0 +1,143 @@
+"""Host replay of the index arithmetic of the moment-phase loads of the tent
+kernel (no GPU): for every degree of 3+1D contexts, the task words of the VALU
+moment loops, the matrix-core top-moment tiles and the LDS regions they address
+are read from the library (its own tables and plan) and every address a lane
+computes is checked against the bounds of the array or region it reads, for
+full and ragged chunks.  The tile list is also rebuilt here independently
+(smallest degrees of 16-blocks of the two monomial lists) and the tiles must
+cover every moment monomial of degree <= 2p-2 exactly once."""
+import ctypes
+from math import comb
+
+import numpy as np
+import pytest
+
+from workloads import configs as C
+
+K_TASK_SLOTS, K_TASK_SLOTS1, K_BLOCK, K_MOM_SLOTS = 6, 2, 256, 6
+
+
+def _tables(ctx, p):
+    from paper_1907_02367_amd import tdg
+
+    L = tdg.lib()
+    f = L.tdg_debug_moment_tables
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 5
+    f.restype = ctypes.c_int
+    info = np.zeros(16, np.int32)
+    assert f(ctx._h, p, info.ctypes.data, None, None, None, None) == 0
+    M, M1, M2, nt2, nt1, ntile = (int(x) for x in info[:6])
+    task2 = np.zeros(max(nt2 * 3, 1), np.int32)
+    task1 = np.zeros(max(nt1 * 3, 1), np.int32)
+    ex = np.zeros(max(ntile * 16, 1), np.int32)
+    mp = np.zeros(max(ntile * 256, 1), np.int32)
+    assert f(ctx._h, p, info.ctypes.data, task2.ctypes.data, task1.ctypes.data, ex.ctypes.data, mp.ctypes.data) == 0
+    keys = ["M", "M1", "M2", "ntask2", "ntask1", "ntile", "Q", "pch", "off_pt", "off_pow", "off_W1", "off_fg",
+            "total", "moment", "n", "pmax"]
+    d = dict(zip(keys, (int(x) for x in info)))
+    return d, task2[: nt2 * 3].view(np.uint32), task1[: nt1 * 3].view(np.uint32), ex[: ntile * 16], mp[: ntile * 256]
+
+
+def _check_tasks(task, ntask, slots, n_idx, max_exp, n):
+    """load_tasks / task_idx: words of task t < ntask only; exponents of the
+    prefix and the run start, run indices < n_idx or 0xFFFF past the run; the
+    runs cover 0..n_idx-1 exactly once."""
+    assert ntask <= slots * K_BLOCK
+    seen = np.zeros(n_idx, np.int64)
+    for t in range(ntask):
+        w0, w1, w2 = (int(x) for x in task[3 * t:3 * t + 3])
+        exps = [(w0 >> (5 * v)) & 31 for v in range(n)]
+        d0 = (w0 >> 15) & 31
+        idx = [w1 & 0xFFFF, w1 >> 16, w2 & 0xFFFF, w2 >> 16]
+        run = [i for i in idx if i != 0xFFFF]
+        assert idx[:len(run)] == run  # no gap inside a run
+        assert sum(exps) + d0 + len(run) - 1 <= max_exp
+        for i in run:
+            assert 0 <= i < n_idx
+            seen[i] += 1
+    assert (seen == 1).all()
+
+
+def _degree_blocks(D):
+    lst = [(a, d - a) for d in range(D + 1) for a in range(d, -1, -1)]
+    nb = (len(lst) + 15) // 16
+    return lst, [sum(lst[16 * i]) for i in range(nb)]
+
+
+@pytest.mark.parametrize("p_max", [8, 5])
+def test_moment_phase_indices_stay_in_bounds_3d(p_max):
+    from paper_1907_02367_amd import tdg
+
+    pr = C.cfg5_cube_3d(m=3, p=p_max, variant="b", regions=1)
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, 0.05, 0.4 * 0.8 ** 4)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max, bind=False)
+    ctx.set_gram_mode(1)
+    n = 3
+    checked_tiles = 0
+    for p in range(1, p_max + 1):
+        d, task2, task1, ex, mp = _tables(ctx, p)
+        assert d["moment"] == 1 and d["n"] == 3
+        M, M1, M2, Q, PCH = d["M"], d["M1"], d["M2"], d["Q"], d["pch"]
+        assert M == comb(p + n + 1, n + 1) and M1 == comb(p - 1 + n + 1, n + 1)
+        assert M2 == comb(max(2 * p - 2, 0) + n + 1, n + 1)
+        E2 = 2 * p - 1
+        # VALU moment tasks (moment_points, face moments, write-back runs)
+        _check_tasks(task2, d["ntask2"], K_TASK_SLOTS, M2, max(2 * p - 2, 0), n)
+        _check_tasks(task1, d["ntask1"], K_TASK_SLOTS1, M, p, n)
+        # LDS regions: powers of the top (E2) and bottom (p+1) points, moments
+        pow_region = d["off_W1"] - d["off_pow"]
+        assert PCH * (n + 1) * E2 + PCH * (n + 1) * (p + 1) <= pow_region
+        assert (n + 1) * M2 + (n + 1) * M1 + M <= d["off_fg"] - d["off_W1"]
+        assert d["total"] * 8 <= 160 * 1024
+        ntile = d["ntile"]
+        if p < 2:
+            assert ntile == 0
+            continue
+        # independent tile list
+        D = 2 * p - 2
+        lst, mins = _degree_blocks(D)
+        expect = [(I, J) for I in range(len(mins)) for J in range(len(mins)) if mins[I] + mins[J] <= D]
+        if len(expect) > 4 * K_MOM_SLOTS:
+            assert ntile == 0
+            continue
+        assert ntile == len(expect)
+        checked_tiles += ntile
+        assert PCH % 4 == 0
+        exps = ex.reshape(ntile, 16)
+        for field, sh in (("a0", 0), ("a1", 5), ("c0", 10), ("c1", 15)):
+            assert ((exps >> sh) & 31).max() < E2, field
+        # rows/columns of each tile carry the exponents of the degree lists
+        for t, (I, J) in enumerate(expect):
+            for l in range(16):
+                i, j = 16 * I + l, 16 * J + l
+                a = lst[i] if i < len(lst) else (0, 0)
+                c = lst[j] if j < len(lst) else (0, 0)
+                assert int(exps[t, l]) == a[0] | a[1] << 5 | c[0] << 10 | c[1] << 15
+        # every moment monomial exactly once in the fold map; entries in range
+        assert mp.min() >= -1 and mp.max() < M2
+        cnt = np.bincount(mp[mp >= 0], minlength=M2)
+        assert (cnt == 1).all()
+        # k-step reads of a full chunk and of the ragged last chunk of an element
+        for nc in {PCH, Q % PCH or PCH, 1}:
+            nks = (nc + 3) // 4
+            lane = np.arange(64)
+            for ks in range(nks):
+                pt = ks * 4 + lane // 16
+                assert pt.max() < PCH  # inside the chunk's regions even for padded points
+                for w in range(4):
+                    for s in range(K_MOM_SLOTS):
+                        t = w + 4 * s
+                        if t >= ntile:
+                            continue
+                        e = exps[t, lane % 16]
+                        base = pt * (n + 1) * E2
+                        for v, sh in enumerate((0, 5, 10, 15)):
+                            addr = base + v * E2 + ((e >> sh) & 31)
+                            assert addr.max() < PCH * (n + 1) * E2
+        # fold reads of mt_map
+        lane = np.arange(64)
+        for t in range(ntile):
+            for r in range(4):
+                idx = t * 256 + ((lane >> 4) + 4 * r) * 16 + (lane & 15)
+                assert idx.max() < ntile * 256
+    assert checked_tiles > 0
