@@ -252,7 +252,9 @@ def tent_pitch(coords, elems, c, T, gamma) -> Tents:
     c = np.ascontiguousarray(c, dtype=np.float64)
     h = ctypes.c_void_p()
     _check(lib().tent_pitch(ctypes.byref(m), _ptr(c), float(T), float(gamma), ctypes.byref(h)))
-    return Tents(h)
+    t = Tents(h)
+    t.T, t.gamma = float(T), float(gamma)
+    return t
 
 
 class Trefftz:

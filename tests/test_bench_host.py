@@ -50,3 +50,26 @@ def test_operation_counts_follow_the_closed_form():
     assert np.allclose(flops, expect)
     assert np.allclose(bytes_, 2.0 * QT * 4 * 8)
     assert (N == 16).all()
+
+
+def test_per_tent_degree_counts_reduce_to_the_fixed_degree_counts():
+    """op_counts_deg (the learned path: a degree per tent) gives op_counts at a
+    uniform degree, and the moment form's executed count is below the
+    quadrature count at 3+1D p = 8 (its reason to exist) but positive."""
+    import bench
+    from paper_1907_02367_amd import tdg
+    from workloads import configs as C
+
+    pr = C.cfg5_cube_3d(m=2, p=8, variant="b", regions=1)
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, 0.05, 0.4 * 0.8 ** 4)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=8, bind=False)
+    f8, b8, N8 = bench.op_counts(ctx, pr, T)
+    fd, bd, Nd = bench.op_counts_deg(ctx, pr, T, np.full(T.n_tents, 8))
+    assert np.allclose(fd, f8) and np.allclose(bd, b8) and np.allclose(Nd, N8)
+    assert (N8 == 285).all()
+    ex = bench.moment_exec_flops(ctx, pr, T, np.full(T.n_tents, 8))
+    assert (ex > 0).all() and (ex < 0.5 * f8).all()
+    p = np.where(np.arange(T.n_tents) % 2 == 0, 5, 8)
+    fm, _, Nm = bench.op_counts_deg(ctx, pr, T, p)
+    assert (fm[p == 5] < f8[p == 5]).all() and np.allclose(fm[p == 8], f8[p == 8])
+    assert set(np.unique(Nm)) == {91, 285}
