@@ -33,7 +33,16 @@ What is computed, following the paper:
 * Recovery of U (Sec. 5): the constant basis function does not enter the
   first-order form; it is fixed per group by one extra row that matches the
   mean of U over the tent's bottom facets with the incoming U (bottom reading
-  of the extra space-like term).
+  of the extra space-like term; recover="mean").  The paper's own recovery
+  (recover="all") adds int_bot U V to the left and int_bot U_bot V to the
+  right for every test function V of U^p (the constant included), with the
+  Trefftz unknowns of U (the constant and the N-1 functions whose derivatives
+  are the first-order basis) solved together: the extra term of Sec. 5 taken
+  on the tent's bottom facets, where the upper element's test function lives.
+
+* Neumann faces (eq. 4.1, T^N): vertical faces above boundary facets of kind
+  1 add int v (tau.n) + beta (sigma.n)(tau.n) to the left and
+  int g_N (beta tau.n - w) to the right.
 
 * Solve: dense LU with partial pivoting (numpy.linalg.solve, LAPACK getrf/getrs).
 
@@ -117,7 +126,7 @@ class Group:
 
 class OracleTDG:
     def __init__(self, coords, elems, c, tents, layer_ptr, p: int, q: int,
-                 alpha: float = 0.5, beta: float = 0.5, gD=None):
+                 alpha: float = 0.5, beta: float = 0.5, gD=None, gN=None, bface_kind=None, recover="mean"):
         self.topo = Topology(coords, elems, c)
         self.n = self.topo.n
         self.tents = list(tents)
@@ -127,6 +136,15 @@ class OracleTDG:
         self.alpha = float(alpha)
         self.beta = float(beta)
         self.gD = gD  # callable (x (Q,n), t (Q,)) -> (Q,), None means g_D = 0
+        self.gN = gN  # same for g_N on Neumann faces
+        assert recover in ("off", "mean", "all")
+        self.recover = recover
+        # kind of every boundary facet (0 Dirichlet, 1 Neumann), in the order of
+        # Topology.boundary_facets(); None: all Dirichlet
+        bf = self.topo.boundary_facets()
+        kinds = np.zeros(len(bf), dtype=np.int64) if bface_kind is None else np.asarray(bface_kind, dtype=np.int64)
+        assert kinds.shape == (len(bf),) and set(np.unique(kinds)) <= {0, 1}
+        self.kind = {ek: int(kd) for ek, kd in zip(bf, kinds)}
         self.lam_ref, self.w_ref = simplex_rule(self.n, self.q)
         X = self.topo.coords[self.topo.elems]  # (ne, n+1, n)
         self.xq = np.einsum("qk,ekd->eqd", self.lam_ref, X)
@@ -234,9 +252,10 @@ class OracleTDG:
             A0[r] += w @ Ub
             A00[r] += w.sum()
             r0[r] += w @ self.U[e]
-            cache[e] = (Vt, St, Ut, Vb, Sb, g_old, g_new, phi_new)
+            cache[e] = (Vt, St, Ut, Vb, Sb, g_old, g_new, phi_new, Ub)
         # Dirichlet faces
         dfaces = []
+        nfaces = []
         for e, k in topo.boundary_facets_at(V):
             r = grp[e]
             G = groups[r]
@@ -248,10 +267,18 @@ class OracleTDG:
             Vf, Sf, _ = G.fields(xs, ts)
             nrm = topo.outward_normal(e, k)
             sn = Sf @ nrm
-            A[b, b] += (Vf * fw[:, None]).T @ (sn + al * Vf)
-            g = self.gD(xs, ts) if self.gD is not None else np.zeros(len(ts))
-            rhs[b] += (fw * g) @ (al * Vf - sn)
-            dfaces.append((r, fw, Vf, Sf, nrm, g))
+            if self.kind[(e, k)] == 0:
+                # Dirichlet: (sigma.n + alpha v) w on the left, g_D (alpha w - tau.n) on the right
+                A[b, b] += (Vf * fw[:, None]).T @ (sn + al * Vf)
+                g = self.gD(xs, ts) if self.gD is not None else np.zeros(len(ts))
+                rhs[b] += (fw * g) @ (al * Vf - sn)
+                dfaces.append((r, fw, Vf, Sf, nrm, g))
+            else:
+                # Neumann: v (tau.n) + beta (sigma.n)(tau.n) on the left, g_N (beta tau.n - w) on the right
+                A[b, b] += (sn * fw[:, None]).T @ (Vf + be * sn)
+                g = self.gN(xs, ts) if self.gN is not None else np.zeros(len(ts))
+                rhs[b] += (fw * g) @ (be * sn - Vf)
+                nfaces.append((r, fw, Vf, Sf, nrm, g))
         # interface faces between speed groups (Sec. 4.2)
         ifaces = []
         for e1, k1, e2, k2 in topo.interface_facets_at(V):
@@ -273,12 +300,35 @@ class OracleTDG:
                         + (tnb * fw[:, None]).T @ (0.5 * sb_ * Va + be * sa * sb_ * sna))
             ifaces.append((r, s, fw, F, nrm))
 
-        sol = np.linalg.solve(A, rhs)
-        a0 = np.array([(r0[r] - A0[r] @ sol[r * NW:(r + 1) * NW]) / A00[r] for r in range(m)])
+        if self.recover == "all":
+            # unknowns per group: the constant, then the N-1 functions; the
+            # first-order form acts on the functions only (the constant has no
+            # derivatives), the bottom mass int_bot U_j U_i couples all of them
+            N = NW + 1
+            Af = np.zeros((m * N, m * N))
+            bf = np.zeros(m * N)
+            for r in range(m):
+                for s_ in range(m):
+                    Af[r * N + 1:(r + 1) * N, s_ * N + 1:(s_ + 1) * N] = A[r * NW:(r + 1) * NW, s_ * NW:(s_ + 1) * NW]
+                bf[r * N + 1:(r + 1) * N] = rhs[r * NW:(r + 1) * NW]
+            for e in P:
+                r = grp[e]
+                w = self.wq[e]
+                Ub = cache[e][8]  # U of the functions at the bottom points
+                Ufull = np.concatenate([np.ones((len(w), 1)), Ub], axis=1)  # (Q, N)
+                Af[r * N:(r + 1) * N, r * N:(r + 1) * N] += (Ufull * w[:, None]).T @ Ufull
+                bf[r * N:(r + 1) * N] += (w * self.U[e]) @ Ufull
+            full = np.linalg.solve(Af, bf)
+            a0 = np.array([full[r * N] for r in range(m)])
+            sol = np.concatenate([full[r * N + 1:(r + 1) * N] for r in range(m)])
+        else:
+            sol = np.linalg.solve(A, rhs)
+            a0 = np.array([(r0[r] - A0[r] @ sol[r * NW:(r + 1) * NW]) / A00[r] if self.recover == "mean" else 0.0
+                           for r in range(m)])
 
         diag = None
         if want_diag:
-            diag = self._diagnostics(P, grp, groups, cache, sol, NW, dfaces, ifaces)
+            diag = self._diagnostics(P, grp, groups, cache, sol, NW, dfaces, ifaces, nfaces)
         # overwrite the stored values with the top values
         for e in P:
             r = grp[e]
@@ -290,7 +340,7 @@ class OracleTDG:
         self.tau[V] = tt
         return sol, a0, diag
 
-    def _diagnostics(self, P, grp, groups, cache, sol, NW, dfaces, ifaces):
+    def _diagnostics(self, P, grp, groups, cache, sol, NW, dfaces, ifaces, nfaces=()):
         """Terms of the per-tent energy balance (derived from eq. 4.1 with w = u
         and the divergence theorem for Trefftz fields)."""
         al, be = self.alpha, self.beta
@@ -299,7 +349,7 @@ class OracleTDG:
             r = grp[e]
             cr = groups[r].c
             x_r = sol[r * NW:(r + 1) * NW]
-            Vt, St, Ut, Vb, Sb, g_old, g_new, _ = cache[e]
+            Vt, St, Ut, Vb, Sb, g_old, g_new, _, _ = cache[e]
             w = self.wq[e]
             vt, st = Vt @ x_r, np.einsum("qjm,j->qm", St, x_r)
             E_top += 0.5 * (w * (vt ** 2 / cr ** 2 + (st ** 2).sum(-1) - 2 * vt * (st @ g_new))).sum()
@@ -315,6 +365,12 @@ class OracleTDG:
             snf = np.einsum("qjm,j->qm", Sf, x_r) @ nrm
             D_bnd += al * (fw * vf ** 2).sum()
             G_bnd += (fw * g * (al * vf - snf)).sum()
+        for r, fw, Vf, Sf, nrm, g in nfaces:
+            x_r = sol[r * NW:(r + 1) * NW]
+            vf = Vf @ x_r
+            snf = np.einsum("qjm,j->qm", Sf, x_r) @ nrm
+            D_bnd += self.beta * (fw * snf ** 2).sum()
+            G_bnd += (fw * g * (self.beta * snf - vf)).sum()
         D_int = 0.0
         for r, s, fw, F, nrm in ifaces:
             xr = sol[r * NW:(r + 1) * NW]
@@ -348,6 +404,13 @@ class OracleTDG:
         e_abs = np.sqrt((self.wq * d2).sum())
         ref = np.sqrt((self.wq * (v_ex ** 2 / c ** 2 + (sig_ex ** 2).sum(-1))).sum())
         return e_abs, (e_abs / ref if ref > 0 else np.inf)
+
+    def error_U(self, U_ex):
+        """||U - U_ex||_L2 on the flat front (Sec. 6.6 reports it) and its
+        ratio to ||U_ex||."""
+        d = np.sqrt((self.wq * (self.U - U_ex) ** 2).sum())
+        ref = np.sqrt((self.wq * U_ex ** 2).sum())
+        return d, (d / ref if ref > 0 else np.inf)
 
     def energy(self):
         """E_phi on the current front (flux form; the paper's E where flat)."""

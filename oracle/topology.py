@@ -52,6 +52,15 @@ class Topology:
             self.grad_lam[e, 0, :] = -Jinv.sum(axis=0)
             self.absdet[e] = abs(np.linalg.det(J))
 
+    def boundary_facets(self):
+        """All boundary facets as (element, opposite local index), ascending:
+        the order in which a per-boundary-facet kind (Dirichlet/Neumann) is
+        given."""
+        if not hasattr(self, "_bfall"):
+            self._bfall = sorted((e, k) for f, sides in self.facets.items() if len(sides) == 1
+                                 for (e, k) in sides)
+        return self._bfall
+
     def boundary_facets_at(self, V):
         """Boundary facets containing V: list of (element, opposite local index)."""
         if not hasattr(self, "_bf"):
