@@ -6,7 +6,8 @@
  * Wintersteiger, "Tent pitching and Trefftz-DG method for the acoustic wave
  * equation" (eq. 2.1):
  *     div sigma + c^-2 dv/dt = 0,   grad v + dsigma/dt = 0   in Omega x (0,T),
- *     v(.,0) = v0, sigma(.,0) = sigma0,  v = g_D on the (Dirichlet) boundary,
+ *     v(.,0) = v0, sigma(.,0) = sigma0,  v = g_D on the Dirichlet boundary,
+ *     sigma.n = g_N on the Neumann boundary,
  * with a wave speed c > 0 that is constant on each spatial element.  With
  * v = dU/dt and sigma = -grad U this is the scalar wave equation (eq. 2.2).
  *
@@ -59,8 +60,11 @@ enum {
 };
 
 /* Spatial simplicial mesh.  coords: nv*dim doubles, vertex-major.
- * elems: ne*(dim+1) vertex indices, element-major.  bface_kind must be NULL:
- * every boundary facet is Dirichlet (the only kind the path supports). */
+ * elems: ne*(dim+1) vertex indices, element-major.  bface_kind: the kind of
+ * every boundary facet, 0 = Dirichlet, 1 = Neumann (eq. 4.1, T^D and T^N), in
+ * ascending (element, local index of the opposite vertex) order, the order
+ * tdg_boundary_facets lists; NULL = every boundary facet Dirichlet.  Other
+ * values: TDG_EINVAL.  The pitcher ignores it. */
 typedef struct {
   int32_t dim, nv, ne;
   const double* coords;
@@ -80,6 +84,10 @@ typedef void* tdg_stream; /* a hipStream_t */
  * Fails with TDG_ENONCAUSAL if a front element would become c|grad phi| >= 1.
  * c: ne speeds.  Requires dim in {1,2,3}, T > 0, gamma > 0. */
 int tent_pitch(const tdg_mesh* mesh, const double* c, double T, double gamma, tdg_tents** out);
+/* The boundary facets of a mesh in the order of tdg_mesh.bface_kind: nbf and
+ * (facets may be NULL) facets[2 i], facets[2 i + 1] = element, local index of
+ * the vertex opposite the facet.  Validates the mesh like tent_pitch. */
+int tdg_boundary_facets(const tdg_mesh* mesh, int64_t* nbf, int32_t* facets);
 /* Layer and tent counts and the largest c|grad phi| over all pitched fronts. */
 int tent_info(const tdg_tents* tents, int32_t* n_layers, int64_t* n_tents, double* max_face_slope);
 /* Copies the tent list: vertex[n_tents], t_bot[n_tents], t_top[n_tents] and
@@ -96,8 +104,14 @@ typedef struct {
   double beta;       /* interface penalty (Sec. 2.4), e.g. 0.5 */
   int32_t precision; /* 0 = FP64; 1 = FP32 matrix-core Gram + FP64 LU + FP64 refinement */
   int32_t layout;    /* must be 1: values stored at spatial quadrature points (Sec. 4.1) */
-  int32_t recover_U; /* 1: one mean-matching row per speed group recovers U (Sec. 5); 0: off;
-                        any other value: TDG_EINVAL */
+  int32_t recover_U; /* recovery of U, the solution of the second-order equation (Sec. 5):
+                        1: one row per speed group matching the mean of U over the tent's
+                           bottom facets with the incoming U ((v, sigma) are exactly eq. 4.1);
+                        2: the paper's terms int_bot U V = int_bot U_bot V added for every
+                           test function V of U^p, the constants solved with the functions
+                           (quadrature Gram only: trefftz_set_gram_mode(1) and precision = 1
+                           are rejected);
+                        0: off; other values: TDG_EINVAL */
 } tdg_opts;
 
 enum {
@@ -106,7 +120,7 @@ enum {
   TDG_BUF_STATE = 2, /* (v, sigma_1..sigma_n, U) at every quadrature point */
   TDG_BUF_STATE0 = 3,/* copy of the initial values (trefftz_reset) */
   TDG_BUF_TAU = 4,   /* advancing front, one time per vertex */
-  TDG_BUF_GD = 5,    /* Dirichlet data at the boundary points */
+  TDG_BUF_GD = 5,    /* boundary data (g_D or g_N) at the boundary points */
   TDG_BUF_WORK = 6,  /* scratch: reductions, error data, device status word */
   TDG_BUF_TENT = 7,  /* per-tent outputs: dissipation, refinement steps */
   TDG_NBUF = 8
@@ -119,9 +133,14 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
 /* Spatial quadrature points, element-major: nq = ne * Q points of dim
  * coordinates.  Pass xq = NULL to query nq.  w (nullable) gets the weights. */
 int trefftz_quad_points(const tdg_ctx* ctx, int64_t* nq, double* xq, double* w);
-/* Space-time points (dim+1 coordinates, time last) of every Dirichlet face of
- * every tent, in tent order; the caller evaluates g_D there.  xt may be NULL. */
+/* Space-time points (dim+1 coordinates, time last) of the boundary faces of
+ * every tent, in tent order, per tent the Dirichlet faces then the Neumann
+ * faces; the caller evaluates g_D or g_N there (trefftz_boundary_kinds).  xt
+ * may be NULL. */
 int trefftz_boundary_points(const tdg_ctx* ctx, int64_t* nb, double* xt);
+/* kind[nb]: 0 where the boundary point lies on a Dirichlet face (g_D), 1 on a
+ * Neumann face (g_N, the prescribed sigma.n). */
+int trefftz_boundary_kinds(const tdg_ctx* ctx, int8_t* kind);
 /* Sizes in bytes of the TDG_NBUF device buffers the caller must provide. */
 int trefftz_buffer_sizes(const tdg_ctx* ctx, int64_t sizes[TDG_NBUF]);
 /* Hands over the device buffers (each at least the queried size, 256-byte
@@ -131,7 +150,8 @@ int trefftz_bind(tdg_ctx* ctx, void* const dev_ptrs[TDG_NBUF], tdg_stream stream
  * (point-major), U0[nq] (nullable = 0).  Also resets the front to t = 0. */
 int trefftz_set_initial(tdg_ctx* ctx, const double* v0, const double* sigma0, const double* U0,
                         tdg_stream stream);
-/* g_D at the boundary points of trefftz_boundary_points (host array, nb). */
+/* Boundary data at the points of trefftz_boundary_points (host array, nb):
+ * g_D at points of Dirichlet faces, g_N at points of Neumann faces. */
 int trefftz_set_boundary(tdg_ctx* ctx, const double* gD, tdg_stream stream);
 /* Restores the initial values and the flat front t = 0 (device-to-device). */
 int trefftz_reset(tdg_ctx* ctx, tdg_stream stream);
@@ -146,6 +166,10 @@ int trefftz_layer_solve(tdg_ctx* ctx, int32_t layer_begin, int32_t layer_end, co
  * errors raised by earlier solves. */
 int trefftz_eval_error(tdg_ctx* ctx, const double* v_ex, const double* sigma_ex, double* e_abs, double* e_rel,
                        tdg_stream stream);
+/* L2 error of U on the flat front t = T (the error Sec. 6.6 reports) against
+ * exact values U_ex[nq] at the quadrature points: e_abs = ||U - U_ex||,
+ * e_rel = e_abs / ||U_ex||.  Synchronises. */
+int trefftz_eval_u_error(tdg_ctx* ctx, const double* U_ex, double* e_abs, double* e_rel, tdg_stream stream);
 /* Energy on the current front, E = 1/2 int c^-2 v^2 + |sigma|^2 - 2 v sigma.grad phi
  * (the energy of Sec. 6.5 where the front is flat), and the sum over tents of
  * the per-tent indicator eta_T (see trefftz_set_indicator; 0 for tents solved

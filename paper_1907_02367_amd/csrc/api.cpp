@@ -53,18 +53,19 @@ struct tdg_ctx {
   int64_t nq = 0, nb = 0;
   std::vector<int64_t> bpt_off;
   std::vector<double> bpts;  // nb * (n+1)
+  std::vector<int8_t> bkind;  // nb: 0 = point of a Dirichlet face (g_D), 1 = of a Neumann face (g_N)
   int max_groups = 1;
   // staged static tables
   std::vector<double> hf64;
   std::vector<int> hi32;
   struct TabOff {
     size_t parent, var, expo, fo_ptr, fo_idx, u_ptr, u_idx, ue_ptr, ue_idx, tr_ptr, tr_j, expo2, K2, task2,
-        task1, mt_ex, mt_map;  // i32
+        task1, mt_ex, mt_map, ev_ab, ev_ex;  // i32
     size_t ue_coef, tr_coef;                                                           // f64
     size_t fo_coef, u_coef, fo_coef32;                 // f64 (fo_coef32: floats packed two per double)
   } toff[kMaxP + 1];
   size_t o_coords, o_c, o_grad, o_det, o_lam, o_w, o_tb, o_tt, o_bpt;         // f64
-  size_t o_elems, o_v2e_ptr, o_v2e, o_vb_ptr, o_vb, o_vi_ptr, o_vi, o_tentV;  // i32
+  size_t o_elems, o_v2e_ptr, o_v2e, o_vb_ptr, o_vb, o_vn_ptr, o_vn, o_vi_ptr, o_vi, o_tentV;  // i32
   TableDesc tabd[kMaxP + 1]{};  // per-degree tables and plan, mirrored on the device
   size_t o_tabd = 0;             // offset (doubles) of the device copy in the FP64 buffer
   int gram_mode = 0;   // 0: Gram of the basis values at the points (matrix cores); 1: from moments
@@ -125,7 +126,8 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
   LdsPlan& L = X->lp;
   int maxpatch = 0;
   for (int v = 0; v < X->topo.nv; ++v) maxpatch = std::max(maxpatch, X->topo.v2e_ptr[v + 1] - X->topo.v2e_ptr[v]);
-  L.S = X->max_groups * Tm.NW;
+  // recover_U = 2: the constant of every speed group joins the unknowns
+  L.S = X->max_groups * (Tm.NW + (X->opts.recover_U == 2 ? 1 : 0));
   L.lda = L.S + 1 + ((L.S + 1) % 2 == 0 ? 1 : 0);
   const int ntd = (Tm.NW + 15) / 16;
   L.NWP = ntd * 16 + 1;
@@ -152,6 +154,8 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
   const int pmax = X->opts.p_max;
   for (int p = 0; p <= kMaxP; ++p) L.nwp[p] = p >= 1 && p <= pmax ? ((X->tabs[p].NW + 15) / 16) * 16 + 1 : 0;
   L.moment = (X->gram_mode == 1 && X->opts.precision == 0) ? 1 : 0;
+  if (L.moment && X->opts.recover_U == 2)
+    return fail(TDG_EINVAL, "the moment Gram does not form the recovery terms of recover_U = 2");
   if (L.moment) {
     // moment mode: W1 holds the moments and the bottom data moments (the Z row of
     // the Gram reuses the latter), later the write-back coefficients with the
@@ -161,6 +165,13 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
       const Table& tb = X->tabs[p];
       mom = std::max(mom, (long long)(n + 1) * tb.M2 + (long long)(n + 1) * tb.M1 + tb.M);
       mom = std::max(mom, (((long long)(n + 2) * tb.M + 3) & ~3LL) + ((long long)tb.ntask1 * kTaskInts + 1) / 2);
+    }
+    for (int p = 1; p <= pmax; ++p) {
+      // the per-face path (speed interfaces, Neumann faces) needs at least one
+      // point per chunk: 4 face-value rows and the point's monomials
+      mom = std::max(mom, 4LL * (((X->tabs[p].NW + 15) / 16) * 16 + 1) + X->tabs[p].M1);
+      // the matrix-core evaluation of the 3+1D write-back
+      if (n == 3 && X->tabs[p].ev_nl) mom = std::max(mom, ev_doubles(p, X->tabs[p].ev_nl));
     }
     for (int p = 1; p <= pmax; ++p)
       if (X->tabs[p].ntask2 > kTaskSlots * kBlock || X->tabs[p].ntask1 > kTaskSlots1 * kBlock)
@@ -212,6 +223,8 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
   auto pow_sz = [&](int p, long long c) { return 2LL * c * (n + 1) * (p + 1); };
   auto mono_sz = [&](int p, long long c) { return (long long)X->tabs[p].M * 2 * c; };
   // W1 also holds the write-back coefficients and the degree-p monomial runs
+  // (the matrix-core evaluation of 3+1D write-backs runs where W1 happens to be
+  // large enough for it, see solve_tent; it does not enlarge this plan)
   auto wb_sz = [&](int p) {
     return (((long long)(n + 2) * X->tabs[p].M + 3) & ~3LL) + ((long long)X->tabs[p].ntask1 * kTaskInts + 1) / 2;
   };
@@ -354,7 +367,9 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   if (opts->layout != 1) return fail(TDG_EINVAL, "layout must be 1 (values at quadrature points)");
   if (opts->precision != 0 && opts->precision != 1) return fail(TDG_EINVAL, "precision must be 0 or 1");
   if (!(opts->alpha > 0) || !(opts->beta > 0)) return fail(TDG_EINVAL, "alpha and beta must be positive");
-  if (opts->recover_U != 0 && opts->recover_U != 1) return fail(TDG_EINVAL, "recover_U must be 0 or 1");
+  if (opts->recover_U < 0 || opts->recover_U > 2) return fail(TDG_EINVAL, "recover_U must be 0, 1 or 2");
+  if (opts->recover_U == 2 && opts->precision != 0)
+    return fail(TDG_EINVAL, "recover_U = 2 (the recovery terms for every test function) needs precision = 0");
   auto X = new tdg_ctx();
   std::unique_ptr<tdg_ctx> guard(X);
   std::string err;
@@ -391,10 +406,14 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     for (int64_t i = 0; i < nt; ++i) {
       const int V = tp.V[i];
       if (tau[V] != tp.tb[i]) return fail(TDG_EINVAL, "tent list does not follow the front");
-      const int nf = X->topo.vb_ptr[V + 1] - X->topo.vb_ptr[V];
+      // the points of the tent's Dirichlet faces, then of its Neumann faces
+      const int nfd = X->topo.vb_ptr[V + 1] - X->topo.vb_ptr[V];
+      const int nf = nfd + X->topo.vn_ptr[V + 1] - X->topo.vn_ptr[V];
       X->bpt_off[i + 1] = X->bpt_off[i] + (int64_t)nf * Q;
       for (int f = 0; f < nf; ++f) {
-        const int e = X->topo.vb[2 * (X->topo.vb_ptr[V] + f)], k = X->topo.vb[2 * (X->topo.vb_ptr[V] + f) + 1];
+        const bool neu = f >= nfd;
+        const int* fl = neu ? &X->topo.vn[2 * (X->topo.vn_ptr[V] + f - nfd)] : &X->topo.vb[2 * (X->topo.vb_ptr[V] + f)];
+        const int e = fl[0], k = fl[1];
         double P[4][4];
         for (int d = 0; d < n; ++d) P[0][d] = P[1][d] = X->topo.coords[(size_t)V * n + d];
         P[0][n] = tp.tb[i];
@@ -412,6 +431,7 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
           for (int l = 0; l <= n; ++l)
             for (int d = 0; d <= n; ++d) y[d] += X->quad.lam[(size_t)qq * (n + 1) + l] * P[l][d];
           X->bpts.insert(X->bpts.end(), y, y + n + 1);
+          X->bkind.push_back(neu ? 1 : 0);
         }
       }
       tau[V] = tp.tt[i];
@@ -437,7 +457,9 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   X->o_v2e_ptr = push(X->hi32, T.v2e_ptr.data(), T.v2e_ptr.size());
   X->o_v2e = push(X->hi32, T.v2e.data(), T.v2e.size());
   X->o_vb_ptr = push(X->hi32, T.vb_ptr.data(), T.vb_ptr.size());
-  X->o_vb = push(X->hi32, T.vb.data(), T.vb.size() ? T.vb.size() : 0);
+  X->o_vb = push(X->hi32, T.vb.data(), T.vb.size());
+  X->o_vn_ptr = push(X->hi32, T.vn_ptr.data(), T.vn_ptr.size());
+  X->o_vn = push(X->hi32, T.vn.data(), T.vn.size());
   X->o_vi_ptr = push(X->hi32, T.vi_ptr.data(), T.vi_ptr.size());
   X->o_vi = push(X->hi32, T.vi.data(), T.vi.size());
   X->o_tentV = push(X->hi32, X->tents.V.data(), X->tents.V.size());
@@ -461,6 +483,8 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     o.task1 = push(X->hi32, tb.task1.data(), tb.task1.size());
     o.mt_ex = push(X->hi32, tb.mt_ex.data(), tb.mt_ex.size());
     o.mt_map = push(X->hi32, tb.mt_map.data(), tb.mt_map.size());
+    o.ev_ab = push(X->hi32, tb.ev_ab.data(), tb.ev_ab.size());
+    o.ev_ex = push(X->hi32, tb.ev_ex.data(), tb.ev_ex.size());
     o.ue_coef = push(X->hf64, tb.ue_coef.data(), tb.ue_coef.size());
     o.tr_coef = push(X->hf64, tb.tr_coef.data(), tb.tr_coef.size());
     o.fo_coef = push(X->hf64, tb.fo_coef.data(), tb.fo_coef.size());
@@ -481,7 +505,7 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   // global system slots are needed if the systems do not fit in LDS in either
   // Gram mode (the mode can be switched after binding)
   bool need_slots = !X->lp.A_in_lds;
-  if (X->opts.precision == 0) {
+  if (X->opts.precision == 0 && X->opts.recover_U != 2) {
     const LdsPlan keep = X->lp;
     X->gram_mode = 1;
     if (plan_lds(X) == TDG_OK && !X->lp.A_in_lds) need_slots = true;
@@ -543,6 +567,32 @@ int trefftz_boundary_points(const tdg_ctx* X, int64_t* nb, double* xt) {
   return TDG_OK;
 }
 
+int trefftz_boundary_kinds(const tdg_ctx* X, int8_t* kind) {
+  if (!X || !kind) return fail(TDG_EINVAL, "NULL argument");
+  std::copy(X->bkind.begin(), X->bkind.end(), kind);
+  return TDG_OK;
+}
+
+int tdg_boundary_facets(const tdg_mesh* mesh, int64_t* nbf, int32_t* facets) {
+  TDG_TRY_BEGIN
+  if (!mesh || !nbf) return fail(TDG_EINVAL, "NULL argument");
+  tdg_mesh m = *mesh;
+  m.bface_kind = nullptr;
+  std::vector<double> ones(std::max(mesh->ne, 0), 1.0);
+  Topology T;
+  std::string err;
+  const int rc = build_topology(m, ones.data(), T, err);
+  if (rc) return fail(rc, err);
+  *nbf = (int64_t)T.bfacets.size();
+  if (facets)
+    for (size_t i = 0; i < T.bfacets.size(); ++i) {
+      facets[2 * i] = T.bfacets[i].first;
+      facets[2 * i + 1] = T.bfacets[i].second;
+    }
+  return TDG_OK;
+  TDG_TRY_END
+}
+
 int trefftz_buffer_sizes(const tdg_ctx* X, int64_t sizes[TDG_NBUF]) {
   if (!X || !sizes) return fail(TDG_EINVAL, "NULL argument");
   for (int i = 0; i < TDG_NBUF; ++i) sizes[i] = X->sizes[i];
@@ -588,6 +638,8 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
   P.v2e = I + X->o_v2e;
   P.vb_ptr = I + X->o_vb_ptr;
   P.vb = I + X->o_vb;
+  P.vn_ptr = I + X->o_vn_ptr;
+  P.vn = I + X->o_vn;
   P.vi_ptr = I + X->o_vi_ptr;
   P.vi = I + X->o_vi;
   P.tent_V = I + X->o_tentV;
@@ -625,6 +677,11 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
     D.mt_ntile = tb.mt_ntile;
     D.mt_ex = I + o.mt_ex;
     D.mt_map = I + o.mt_map;
+    D.ev_nl = tb.ev_nl;
+    D.ev_nat = tb.ev_nat;
+    for (int i = 0; i < 8; ++i) D.ev_nks[i] = tb.ev_nks[i];
+    D.ev_ab = I + o.ev_ab;
+    D.ev_ex = I + o.ev_ex;
     D.fo_nnz = (int)tb.fo_idx.size();
     D.u_nnz = (int)tb.u_idx.size();
     D.ue_n = tb.ue_ptr.back();
@@ -854,6 +911,24 @@ int trefftz_eval_error(tdg_ctx* X, const double* v_ex, const double* sigma_ex, d
   return std::isfinite(ea) ? TDG_OK : fail(TDG_ENAN, "non-finite error");
 }
 
+int trefftz_eval_u_error(tdg_ctx* X, const double* U_ex, double* e_abs, double* e_rel, tdg_stream stream) {
+  if (!X || !U_ex) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  hipStream_t s = (hipStream_t)stream;
+  double* W = (double*)X->dev[TDG_BUF_WORK];
+  HIP_OK(hipMemcpyAsync(W + X->w_ex, U_ex, X->nq * 8, hipMemcpyHostToDevice, s));
+  if (launch_norms(X->kp, 2, W + X->w_ex, W + X->w_partial, X->nblocks_red, W + X->w_out, stream))
+    return fail(TDG_EHIP, "reduction launch failed");
+  double out[2];
+  HIP_OK(hipMemcpyAsync(out, W + X->w_out, 16, hipMemcpyDeviceToHost, s));
+  int rc = read_status(X, s);
+  if (rc) return rc;
+  const double ea = std::sqrt(out[0]);
+  if (e_abs) *e_abs = ea;
+  if (e_rel) *e_rel = out[1] > 0 ? ea / std::sqrt(out[1]) : INFINITY;
+  return std::isfinite(ea) ? TDG_OK : fail(TDG_ENAN, "non-finite error");
+}
+
 int trefftz_energy(tdg_ctx* X, double* E_front, double* dissipated, tdg_stream stream) {
   if (!X) return fail(TDG_EINVAL, "NULL argument");
   if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
@@ -1048,6 +1123,22 @@ int tdg_debug_moment_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t*
   if (task1) std::copy(t.task1.begin(), t.task1.end(), task1);
   if (mt_ex) std::copy(t.mt_ex.begin(), t.mt_ex.end(), mt_ex);
   if (mt_map) std::copy(t.mt_map.begin(), t.mt_map.end(), mt_map);
+  return TDG_OK;
+}
+
+// Internal (host-side index replay in the tests): the matrix-core evaluation
+// tables of degree p.  info[12] = {ev_nl, ev_nat, ev_nks[0..7], M, W1 doubles}.
+int tdg_debug_eval_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t* ev_ab, int32_t* ev_ex) {
+  if (!X || !info) return fail(TDG_EINVAL, "NULL argument");
+  if (p < 1 || p > X->opts.p_max) return fail(TDG_EINVAL, "p out of range");
+  const Table& t = X->tabs[p];
+  info[0] = t.ev_nl;
+  info[1] = t.ev_nat;
+  for (int i = 0; i < 8; ++i) info[2 + i] = t.ev_nks[i];
+  info[10] = t.M;
+  info[11] = X->lp.off_fg - X->lp.off_W1;
+  if (ev_ab) std::copy(t.ev_ab.begin(), t.ev_ab.end(), ev_ab);
+  if (ev_ex) std::copy(t.ev_ex.begin(), t.ev_ex.end(), ev_ex);
   return TDG_OK;
 }
 

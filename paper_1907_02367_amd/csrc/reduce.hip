@@ -3,7 +3,9 @@
 //           sum w (c^-2 (v - v_ex)^2 + |sigma - sigma_ex|^2) and the same norm of
 //           the exact values;
 //   kind 1: energy on the current front (Sec. 6.5 in flux form),
-//           1/2 sum w (c^-2 v^2 + |sigma|^2 - 2 v sigma.grad phi).
+//           1/2 sum w (c^-2 v^2 + |sigma|^2 - 2 v sigma.grad phi);
+//   kind 2: L2 error of U on the flat front (Sec. 6.6) against exact values,
+//           sum w (U - U_ex)^2 and sum w U_ex^2.
 // Two passes: fixed grid of blocks -> per-block partial sums (tree order),
 // then one block sums the partials in a fixed order.  No floating-point atomics.
 #include <hip/hip_runtime.h>
@@ -54,6 +56,10 @@ __global__ __launch_bounds__(kRB) void norms_kernel(KParams P, int kind, const d
       }
       s0 += w * a;
       s1 += w * b;
+    } else if (kind == 2) {
+      const double du = st[(NS + 1) * Q + q] - ex[i];
+      s0 += w * du * du;
+      s1 += w * ex[i] * ex[i];
     } else {
       const int* vs = P.elems + (size_t)e * (NS + 1);
       const double* gl = P.grad_lam + (size_t)e * (NS + 1) * NS;

@@ -57,6 +57,14 @@ struct TableDesc {
   int mt_ntile;
   const int* mt_ex;
   const int* mt_map;
+  // matrix-core evaluation of the solution at points (3+1D): monomial k of
+  // degree <= p is L_a(t, x1) R_b(x2, x3); ev_ab[k] = a | b << 16; ev_ex[i] =
+  // e_first | e_second << 8 of entry i of the (shared) two-variable list of
+  // degree <= p (ev_nl entries, by degree); ev_nat tiles of 16 L entries, tile I
+  // needs ev_nks[I] steps of 4 R entries; ev_nl = 0: not used at this degree
+  int ev_nl, ev_nat, ev_nks[8];
+  const int* ev_ab;
+  const int* ev_ex;
   // entry form: entries of basis function j+1 are ue_ptr[j]..ue_ptr[j+1]-1; entry e
   // holds (n+2) pairs (monomial index, coefficient) for U, v = dU/dt and
   // sigma_m = -dU/dx_m: ue_idx[e*(n+2)+s], ue_coef[e*(n+2)+s] (coefficient 0 if absent)
@@ -96,8 +104,10 @@ struct KParams {
   const int* elems;        // ne*(n+1)
   const int* v2e_ptr;      // nv+1
   const int* v2e;
-  const int* vb_ptr;       // nv+1: boundary facets containing V
+  const int* vb_ptr;       // nv+1: Dirichlet boundary facets containing V
   const int* vb;           // pairs (element, local index of the opposite vertex)
+  const int* vn_ptr;       // nv+1: Neumann boundary facets containing V
+  const int* vn;           // pairs, as vb
   const int* vi_ptr;       // nv+1: speed-interface facets containing V
   const int* vi;           // quadruples (e1, k1, e2, k2), e1 < e2
   // tents
@@ -155,6 +165,14 @@ struct LdsPlan {
   int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, off_fg, off_AF, off_vec, total;
 };
 
+// LDS doubles of the matrix-core evaluation at degree p (3+1D): the dense
+// coefficients of the n+2 fields over (L entry, R entry) pairs, the powers of
+// 16 points per wave (4 waves, n+1 variables, exponents 0..p), the entry list
+constexpr int ev_ldb(int nl) { return nl | 1; }
+constexpr long long ev_doubles(int p, int nl) {
+  return 5LL * (16 * ((nl + 15) / 16)) * ev_ldb(nl) + 4LL * 16 * 4 * (p + 1) + (nl + 1) / 2 + 1;
+}
+
 // LDS workspace (doubles) of the blocked LU of an S x (S+1) system with panels
 // of nb columns: the panel (column stride S|1), the U12 rows (row stride
 // (S+1)|1), then S + nb + 1 ints (row origins, pivots, one spare).
@@ -185,7 +203,9 @@ struct Topology {
   std::vector<double> absdet;     // ne
   std::vector<int> v2e_ptr, v2e;  // patches (ascending element)
   std::vector<int> nb_ptr, nb;    // neighbours (ascending)
-  std::vector<int> vb_ptr, vb;    // boundary facets at V
+  std::vector<int> vb_ptr, vb;    // Dirichlet boundary facets at V: (element, opposite local vertex)
+  std::vector<int> vn_ptr, vn;    // Neumann boundary facets at V
+  std::vector<std::pair<int, int>> bfacets;  // every boundary facet, ascending (element, local vertex)
   std::vector<int> vi_ptr, vi;    // interface facets at V
 };
 
@@ -208,6 +228,8 @@ struct Table {
   int ntask2 = 0, ntask1 = 0;
   int mt_ntile = 0;                // matrix-core top-moment tiles (see TableDesc)
   std::vector<int> mt_ex, mt_map;
+  int ev_nl = 0, ev_nat = 0, ev_nks[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // matrix-core evaluation (see TableDesc)
+  std::vector<int> ev_ab, ev_ex;
   std::vector<int> parent, var;
   std::vector<int> expo;  // M*(n+1): k, alpha_1..alpha_n
   std::vector<int> fo_ptr, fo_idx;

@@ -495,28 +495,50 @@ __device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, c
   const int tid = threadIdx.x;
   const double ca = alpha * cr * cr;
   for (int i = 0; i < NW; ++i) {
-    for (int l = tid; l < M1; l += blockDim.x)
-      for (int c = 0; c <= NS; ++c) Z[c * M1 + l] = 0.0;
-    const int amax = dirichlet ? 0 : NS;
-    for (int a = 0; a <= amax; ++a) {
-      const int row = i * (NS + 1) + a;
-      for (int e = fo_ptr[row]; e < fo_ptr[row + 1]; ++e) {
-        const int k = fo_idx[e];
-        const double al = fo_coef[e];
-        const int* K2r = K2 + k * M1;
-        for (int l = tid; l < M1; l += blockDim.x) {
-          const int b2 = K2r[l];
-          if (dirichlet) {
-            Z[l] += ca * al * NU[b2];
-            for (int d = 0; d < NS; ++d) Z[(1 + d) * M1 + l] += cr * al * NU[(1 + d) * M2 + b2];
-          } else if (a == 0) {
-            Z[l] += al * NU[b2];
-            for (int d = 0; d < NS; ++d) Z[(1 + d) * M1 + l] -= cr * al * NU[(1 + d) * M2 + b2];
-          } else {
-            Z[a * M1 + l] += al * NU[b2];
-            Z[l] -= cr * al * NU[a * M2 + b2];
+    // Z[b][l] of test function i: each thread keeps the columns l = tid + s*blockDim.x
+    // (two per pass) in registers over all table terms of i, in term order
+    for (int l0 = 0; l0 < M1; l0 += 2 * (int)blockDim.x) {
+      double z[2][NS + 1];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int c = 0; c <= NS; ++c) z[s][c] = 0.0;
+      const int amax = dirichlet ? 0 : NS;
+      for (int a = 0; a <= amax; ++a) {
+        const int row = i * (NS + 1) + a;
+        for (int e = fo_ptr[row]; e < fo_ptr[row + 1]; ++e) {
+          const int k = fo_idx[e];
+          const double al = fo_coef[e];
+          const int* K2r = K2 + k * M1;
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const int l = l0 + tid + s * (int)blockDim.x;
+            if (l < M1) {
+              const int b2 = K2r[l];
+              if (dirichlet) {
+                z[s][0] += ca * al * NU[b2];
+#pragma unroll
+                for (int d = 0; d < NS; ++d) z[s][1 + d] += cr * al * NU[(1 + d) * M2 + b2];
+              } else if (a == 0) {
+                z[s][0] += al * NU[b2];
+#pragma unroll
+                for (int d = 0; d < NS; ++d) z[s][1 + d] -= cr * al * NU[(1 + d) * M2 + b2];
+              } else {
+#pragma unroll
+                for (int c = 1; c <= NS; ++c)
+                  if (c == a) z[s][c] += al * NU[b2];
+                z[s][0] -= cr * al * NU[a * M2 + b2];
+              }
+            }
           }
         }
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int l = l0 + tid + s * (int)blockDim.x;
+        if (l < M1)
+#pragma unroll
+          for (int c = 0; c <= NS; ++c) Z[c * M1 + l] = z[s][c];
       }
     }
     __syncthreads();
@@ -964,6 +986,82 @@ __device__ inline void eval_runs(const Tab& T, const int* runs, const double* va
   }
 }
 
+// Fields of a solution at 16 points per wave on the FP64 matrix cores (3+1D).
+// A monomial of degree <= p is L_a(th, xh1) R_b(xh2, xh3) (entries a, b of the
+// two-variable list EX, by degree), so field c at point pt is
+//   val_c(pt) = sum_a L_a(pt) Y_c[pt][a],   Y_c[pt][a] = sum_b R_b(pt) CM_c[a][b],
+// with CM_c the dense coefficients (rows a < nA16, row stride ldb).  Y is a
+// 16x16x4 MFMA chain per tile of 16 entries a (A: R_b at point l%16, entry b =
+// 4 ks + l/16; B: CM_c[a = 16 I + l%16][b]); tile I needs nks[I] steps (the
+// entries b of degree <= p minus the tile's smallest degree).  Each lane then
+// weights its four results (points l/16 + 4r, entry 16 I + l%16) by L_a and
+// the 16 lanes of a row are summed: every lane of row l/16 ends with val[c][r]
+// of point l/16 + 4r.  PWW: powers of the wave's 16 points, PWW[(pt*4 + v)*P1
+// + e] = var_v^e (v = 0: th).
+template <int NC>
+__device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl, int nat, const int* nks,
+                                   const int* EX, const double* PWW, int P1, double (&val)[NC][4]) {
+  const int lane = threadIdx.x & 63;
+  const int pi = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) val[c][r] = 0.0;
+  for (int I = 0; I < nat; ++I) {
+    const int a = I * 16 + pi;
+    const int ea = a < nl ? EX[a] : 0;
+    double La[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double* pw = PWW + (kq + 4 * r) * 4 * P1;
+      La[r] = a < nl ? pw[ea & 255] * pw[P1 + (ea >> 8)] : 0.0;
+    }
+    const int nk = nks[I];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+      for (int ks = 0; ks < nk; ++ks) {
+        const int b = ks * 4 + kq;
+        double av = 0.0, bv = 0.0;
+        if (b < nl) {
+          const int eb = EX[b];
+          const double* pw = PWW + pi * 4 * P1;
+          av = pw[2 * P1 + (eb & 255)] * pw[3 * P1 + (eb >> 8)];
+          bv = CMd[((long long)c * nA16 + a) * ldb + b];
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) val[c][r] += acc[r] * La[r];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) val[c][r] += __shfl_xor(val[c][r], off, 64);
+}
+
+// Dense coefficients CM_c[a][b] of the fields of group r's solution xs (3+1D):
+// the transposed table contracted with the coefficients, scattered by ev_ab;
+// the U row scaled by h (U_j = h Uhat_j).  Whole workgroup; ends with a barrier.
+template <int NS>
+__device__ inline void build_cm_dense(const Tab& T, const TableDesc& Dp, const double* xr, double hr, double* CMd,
+                                      int nA16, int ldb) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < (NS + 2) * nA16 * ldb; i += blockDim.x) CMd[i] = 0.0;
+  __syncthreads();
+  for (int row = tid; row < (NS + 2) * T.M; row += blockDim.x) {
+    double acc = 0.0;
+    for (int e = T.tr_ptr[row]; e < T.tr_ptr[row + 1]; ++e) acc += T.tr_coef[e] * xr[T.tr_j[e]];
+    const int comp = row / T.M, k = row % T.M;
+    const int ab = Dp.ev_ab[k];
+    CMd[((long long)comp * nA16 + (ab & 0xFFFF)) * ldb + (ab >> 16)] = comp == NS + 1 ? acc * hr : acc;
+  }
+  __syncthreads();
+}
+
 template <int NS, int TPW, bool MIXED, bool MOM>
 __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, double* lds) {
   __shared__ int s_m, s_piv, s_err, s_goff[kMaxGroups + 1], s_conv;
@@ -1154,8 +1252,12 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   }
   __syncthreads();
   const int m = s_m;
-  const int S = m * NW;
-  if (s_err || S > L.S) {
+  // recover_U = 2 (Sec. 5, every test function): the constants of the groups
+  // are unknowns S0 .. S0+m-1 after the functions; the right-hand side is column S
+  const bool R2 = P.recover_U == 2;
+  const int S0 = m * NW;
+  const int S = S0 + (R2 ? m : 0);
+  if (s_err || S > L.S || (MOM && R2)) {
     if (tid == 0) atomicOr(P.status, s_err ? s_err : kStatSize);
     return;
   }
@@ -1369,7 +1471,7 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
         const double sw = sqrt(w), swD = sqrt(w * PS[pt]);
         double f[NS + 1], fb[NS + 1], ub = 0.0;
         eval_j<NS, false>(T, j, MT, LD2, pt, f, &ub);
-        if (pass == 0) eval_j<NS, true>(T, j, MT, LD2, PCH + pt, fb, &ub);
+        if (pass == 0 || R2) eval_j<NS, true>(T, j, MT, LD2, PCH + pt, fb, &ub);
         const double v = cr * f[0];
         if (MIXED && use32) {
           float* row = PSI32 + (size_t)pt * (NS + 1) * NWP + j;
@@ -1383,9 +1485,13 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
         if (pass == 0) {
           double accb = cr * fb[0] * PD[pt * (NS + 2)];
           for (int d = 0; d < NS; ++d) accb += fb[1 + d] * PD[pt * (NS + 2) + 1 + d];
+          // R2: int_bot U_bot U_i joins the right-hand side of function i
+          if (R2) accb += PD[pt * (NS + 2) + NS + 1] * hr * ub;
           RB[pt * NWP + j] = accb;
-          UB[pt * NWP + j] = w * hr * ub;
         }
+        // recovery row sum_q w U_j, or (R2) sqrt(w) U_j: the rows of the bottom
+        // mass Gram sum_q w U_i U_j, formed on the matrix cores with the top Gram
+        if (pass == 0 || R2) UB[pt * NWP + j] = (R2 ? sqrt(w) : w) * hr * ub;
       }
       // zero the padding columns of PSI so the 16-wide tiles see zeros
       for (int i = tid; i < PCH * (NS + 1) * padc; i += blockDim.x) {
@@ -1395,6 +1501,8 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
         else
           PSI[row * NWP + col] = 0.0;
       }
+      if (R2)
+        for (int i = tid; i < PCH * padc; i += blockDim.x) UB[(i / padc) * NWP + NW + i % padc] = 0.0;
       __syncthreads();
       // Gram on the matrix cores: lane l of a k-step reads row 4 ks + l/16, column 16 I + l%16
       {
@@ -1415,6 +1523,16 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
               if (tI[t] >= 0)
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowp[tI[t] * 16], rowp[tJ[t] * 16], acc[t], 0, 0, 0);
           }
+          // R2: bottom mass sum_q w U_i U_j (rows sqrt(w) U of the chunk's points;
+          // rows past nc hold zero weights, PCH is a multiple of 4)
+          if (R2)
+            for (int ks = 0; ks < (nc + 3) / 4; ++ks) {
+              const double* rowp = UB + (size_t)(ks * 4 + (lane >> 4)) * NWP + (lane & 15);
+#pragma unroll
+              for (int t = 0; t < TPW; ++t)
+                if (tI[t] >= 0)
+                  acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowp[tI[t] * 16], rowp[tJ[t] * 16], acc[t], 0, 0, 0);
+            }
         }
       }
       // right-hand side and recovery row: column sums over the chunk's points
@@ -1422,7 +1540,7 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
         double s1 = 0.0, s2 = 0.0;
         for (int pt = 0; pt < nc; ++pt) {
           s1 += RB[pt * NWP + j];
-          s2 += UB[pt * NWP + j];
+          s2 += R2 ? sqrt(PW[pt]) * UB[pt * NWP + j] : UB[pt * NWP + j];
         }
         if (j == tid) {
           rhs_acc += s1;
@@ -1478,6 +1596,21 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   }
 
   }  // quadrature Gram
+  if (R2) {
+    // the constant's row (test function 1) and column (trial constant) of each
+    // group: sum_q w U_j, sum_q w, and the right-hand side sum_q w U_bot
+    for (int i = tid; i < m * NW; i += blockDim.x) {
+      const int r = i / NW, j = i % NW;
+      const double v = A0[r * NWP + j];
+      A[(long long)(S0 + r) * lda + r * NW + j] = v;
+      A[(long long)(r * NW + j) * lda + S0 + r] = v;
+    }
+    if (tid < m) {
+      A[(long long)(S0 + tid) * lda + S0 + tid] = A00[tid];
+      A[(long long)(S0 + tid) * lda + S] = r0[tid];
+    }
+    __syncthreads();
+  }
 
   // ---- 3. time-like faces above facets containing V ---------------------------------
   const int nbf = P.vb_ptr[V + 1] - P.vb_ptr[V];
@@ -1806,17 +1939,19 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     }
     }  // quadrature faces
   }
-  // 3b. speed interfaces, one face at a time (chunks of PCI points; in moment mode
-  //     the monomials sit in W1 behind the face values)
+  // 3b. speed interfaces, then Neumann faces (eq. 4.1, T^N), one face at a time
+  //     (chunks of PCI points; in moment mode the monomials sit in W1 behind the
+  //     face values)
   double* MTI = MOM ? W1 + 4 * PCI * NWP : MT;
-  for (int f = nbf; f < nbf + nif; ++f) {
-    const bool dir = false;
+  const int nnf = P.vn_ptr[V + 1] - P.vn_ptr[V];
+  for (int f = 0; f < nif + nnf; ++f) {
+    const bool dir = f >= nif;  // a Neumann face: one side, data g_N
     int e1, k1, e2 = -1;
     if (dir) {
-      e1 = P.vb[2 * (P.vb_ptr[V] + f)];
-      k1 = P.vb[2 * (P.vb_ptr[V] + f) + 1];
+      e1 = P.vn[2 * (P.vn_ptr[V] + f - nif)];
+      k1 = P.vn[2 * (P.vn_ptr[V] + f - nif) + 1];
     } else {
-      const int* q4 = P.vi + 4 * (P.vi_ptr[V] + f - nbf);
+      const int* q4 = P.vi + 4 * (P.vi_ptr[V] + f);
       e1 = q4[0];
       k1 = q4[1];
       e2 = q4[2];
@@ -1877,7 +2012,8 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     double nrm[NS];
     for (int d = 0; d < NS; ++d) nrm[d] = fsc[1 + d];
     const int ga = s_piv / 16, gb = s_piv % 16;
-    const long long goff = P.bpt_off[tent] + (long long)f * Q;
+    // g_N of a Neumann face: after the tent's Dirichlet faces in the boundary data
+    const long long goff = P.bpt_off[tent] + (long long)(nbf + f - nif) * Q;
     for (int q0 = 0; q0 < Q; q0 += PCI) {
       const int nc = min(PCI, Q - q0);
       const int nside = dir ? 1 : 2;
@@ -1915,9 +2051,10 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
           double sn = 0.0;
           for (int d = 0; d < NS; ++d) sn += fl[1 + d] * nrm[d];
           if (dir) {
-            F1[pt * NWP + j] = sw * v;
-            F1[(PCI + pt) * NWP + j] = sw * (P.alpha * v + sn);
-            F1[(2 * PCI + pt) * NWP + j] = w * g * (P.alpha * v - sn);
+            // test tau_i.n, trial v_j + beta sigma_j.n; data g_N (beta tau_i.n - w_i)
+            F1[pt * NWP + j] = sw * sn;
+            F1[(PCI + pt) * NWP + j] = sw * (v + P.beta * sn);
+            F1[(2 * PCI + pt) * NWP + j] = w * g * (P.beta * sn - v);
           } else {
             F1[((2 * side) * PCI + pt) * NWP + j] = sw * v;
             F1[((2 * side + 1) * PCI + pt) * NWP + j] = sw * sn;
@@ -1930,12 +2067,12 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
           const int ii = idx / NW, jj = idx % NW;
           double acc = 0.0;
           for (int k = 0; k < nc; ++k) acc += F1[k * NWP + ii] * F1[(PCI + k) * NWP + jj];
-          A[(long long)(ga * NW + ii) * lda + ga * NW + jj] += acc;
+          AT[(long long)(ga * NW + ii) * lda + ga * NW + jj] += acc;
         }
         for (int j = tid; j < NW; j += blockDim.x) {
           double acc = 0.0;
           for (int k = 0; k < nc; ++k) acc += F1[(2 * PCI + k) * NWP + j];
-          A[(long long)(ga * NW + j) * lda + S] += acc;
+          AT[(long long)(ga * NW + j) * lda + S] += acc;
         }
       } else {
         // test in group b (sign sb), trial in group a (sign sa):
@@ -2138,9 +2275,13 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   }  // attempts
   if (MIXED && tid == 0 && P.ir_steps) P.ir_steps[tent] = ir_steps + (use32 ? 0 : 1000);
   if (tid < m) {
-    double s = r0[tid];
-    for (int j = 0; j < NW; ++j) s -= A0[tid * NWP + j] * xs[tid * NW + j];
-    a0[tid] = P.recover_U ? s / A00[tid] : 0.0;
+    if (R2) {
+      a0[tid] = xs[S0 + tid];
+    } else {
+      double s = r0[tid];
+      for (int j = 0; j < NW; ++j) s -= A0[tid * NWP + j] * xs[tid * NW + j];
+      a0[tid] = P.recover_U ? s / A00[tid] : 0.0;
+    }
   }
   __syncthreads();
 
@@ -2160,6 +2301,70 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
     for (int r = 0; r < m; ++r) {
       const double cr = gc[r], hr = gh[r];
       const double ic2 = 1.0 / (cr * cr);
+      const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
+      bool ev_mt = false;
+      if constexpr (NS == 3) ev_mt = Dp.ev_nl > 0 && (long long)(L.off_fg - L.off_W1) >= ev_doubles(p, Dp.ev_nl);
+      if constexpr (NS == 3) {
+        if (ev_mt) {
+          // fields at the bottom points on the matrix cores, 16 points per wave
+          const int nl = Dp.ev_nl, nat = Dp.ev_nat, nA16 = 16 * nat, ldb = ev_ldb(nl), P1 = p + 1;
+          double* CMd = W1;
+          double* PWW = W1 + (long long)(NS + 2) * nA16 * ldb;
+          int* EXs = reinterpret_cast<int*>(PWW + 4 * 16 * 4 * P1);
+          __syncthreads();
+          for (int i = tid; i < nl; i += blockDim.x) EXs[i] = Dp.ev_ex[i];
+          build_cm_dense<NS>(T, Dp, xs + r * NW, hr, CMd, nA16, ldb);
+          double* pwv = PWW + wave * 16 * 4 * P1;
+          for (int blk = 0; blk < npts; blk += 64) {
+            if (lane < 16) {
+              const int f = min(blk + wave * 16 + lane, npts - 1);
+              const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+              const double* lam = P.lam_ref + (size_t)(f % Q) * (NS + 1);
+              double var[NS + 1], phi = 0.0;
+              for (int d = 1; d <= NS; ++d) var[d] = 0.0;
+              for (int k = 0; k <= NS; ++k) {
+                phi += lam[k] * R[El<NS>::TAU + k];
+                for (int d = 0; d < NS; ++d) var[1 + d] += lam[k] * R[El<NS>::X + k * NS + d];
+              }
+              var[0] = cr * (phi - tmid) / hr;
+              for (int d = 0; d < NS; ++d) var[1 + d] = (var[1 + d] - XV[d]) / hr;
+              for (int v = 0; v <= NS; ++v) {
+                double a = 1.0;
+                for (int e = 0; e < P1; ++e) {
+                  pwv[(lane * 4 + v) * P1 + e] = a;
+                  a *= var[v];
+                }
+              }
+            }
+            wave_sync();
+            double val[NS + 1][4];
+            eval16_mfma<NS + 1>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, EXs, pwv, P1, val);
+            if ((lane & 15) == 0) {
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int f = blk + wave * 16 + (lane >> 4) + 4 * rr;
+                if (f < npts) {
+                  const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+                  const int q = f % Q;
+                  const int e = (int)R[El<NS>::E];
+                  const double w = P.w_ref[q] * R[El<NS>::DET];
+                  const double* st = P.state + (size_t)e * (NS + 2) * Q;
+                  const double dv = cr * val[0][rr] - st[q];
+                  double ds2 = 0.0, dsg = 0.0;
+                  for (int d = 0; d < NS; ++d) {
+                    const double ds = val[1 + d][rr] - st[(1 + d) * Q + q];
+                    ds2 += ds * ds;
+                    dsg += ds * R[El<NS>::GOLD + d];
+                  }
+                  eta_loc += 0.5 * w * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
+                }
+              }
+            }
+            wave_sync();
+          }
+          continue;
+        }
+      }
       __syncthreads();
       for (int row = tid; row < (NS + 1) * T.M; row += blockDim.x) {
         double acc = 0.0;
@@ -2167,7 +2372,6 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
         cm[row] = acc;
       }
       __syncthreads();
-      const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
       for (int f = tid; f < npts; f += blockDim.x) {
         const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
         const int q = f % Q;
@@ -2218,6 +2422,69 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
   // ---- 6. top values overwrite the stored values -----------------------------------
   for (int r = 0; r < m; ++r) {
     const double cr = gc[r], hr = gh[r];
+    if constexpr (NS == 3) {
+      if (Dp.ev_nl > 0 && (long long)(L.off_fg - L.off_W1) >= ev_doubles(p, Dp.ev_nl)) {
+        // (v, sigma, U) at the top points on the matrix cores, 16 points per wave
+        const int npts = (s_goff[r + 1] - s_goff[r]) * Q;
+        const int nl = Dp.ev_nl, nat = Dp.ev_nat, nA16 = 16 * nat, ldb = ev_ldb(nl), P1 = p + 1;
+        double* CMd = W1;
+        double* PWW = W1 + (long long)(NS + 2) * nA16 * ldb;
+        int* EXs = reinterpret_cast<int*>(PWW + 4 * 16 * 4 * P1);
+        __syncthreads();
+        for (int i = tid; i < nl; i += blockDim.x) EXs[i] = Dp.ev_ex[i];
+        build_cm_dense<NS>(T, Dp, xs + r * NW, hr, CMd, nA16, ldb);
+        double* pwv = PWW + wave * 16 * 4 * P1;
+        for (int blk = 0; blk < npts; blk += 64) {
+          if (lane < 16) {
+            const int f = min(blk + wave * 16 + lane, npts - 1);
+            const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+            const int lV = (int)R[El<NS>::LV];
+            const double* lam = P.lam_ref + (size_t)(f % Q) * (NS + 1);
+            double var[NS + 1], phi = 0.0;
+            for (int d = 1; d <= NS; ++d) var[d] = 0.0;
+            for (int k = 0; k <= NS; ++k) {
+              phi += lam[k] * R[El<NS>::TAU + k];
+              for (int d = 0; d < NS; ++d) var[1 + d] += lam[k] * R[El<NS>::X + k * NS + d];
+            }
+            phi += lam[lV] * dt;
+            var[0] = cr * (phi - tmid) / hr;
+            for (int d = 0; d < NS; ++d) var[1 + d] = (var[1 + d] - XV[d]) / hr;
+            for (int v = 0; v <= NS; ++v) {
+              double a = 1.0;
+              for (int e = 0; e < P1; ++e) {
+                pwv[(lane * 4 + v) * P1 + e] = a;
+                a *= var[v];
+              }
+            }
+          }
+          wave_sync();
+          double val[NS + 2][4];
+          eval16_mfma<NS + 2>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, EXs, pwv, P1, val);
+          if ((lane & 15) == 0) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              const int f = blk + wave * 16 + (lane >> 4) + 4 * rr;
+              if (f < npts) {
+                const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+                const int q = f % Q;
+                const int e = (int)R[El<NS>::E];
+                double* st = P.state + (size_t)e * (NS + 2) * Q;
+                st[q] = cr * val[0][rr];
+#pragma unroll
+                for (int d = 0; d < NS; ++d) st[(1 + d) * Q + q] = val[1 + d][rr];
+                st[(NS + 1) * Q + q] = a0[r] + val[NS + 1][rr];
+                bool fin = true;
+#pragma unroll
+                for (int c = 0; c < NS + 2; ++c) fin = fin && isfinite(val[c][rr]);
+                if (!fin) atomicOr(P.status, kStatNan);
+              }
+            }
+          }
+          wave_sync();
+        }
+        continue;
+      }
+    }
     __syncthreads();
     for (int row = tid; row < (NS + 2) * T.M; row += blockDim.x) {
       double acc = 0.0;

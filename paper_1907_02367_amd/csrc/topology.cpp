@@ -57,10 +57,6 @@ int build_topology(const tdg_mesh& m, const double* c, Topology& T, std::string&
     err = "empty mesh or NULL array";
     return TDG_EINVAL;
   }
-  if (m.bface_kind) {
-    err = "only Dirichlet boundaries are supported (bface_kind must be NULL)";
-    return TDG_EINVAL;
-  }
   T.n = n;
   T.nv = m.nv;
   T.ne = m.ne;
@@ -185,9 +181,26 @@ int build_topology(const tdg_mesh& m, const double* c, Topology& T, std::string&
       err = "non-manifold mesh: a facet shared by more than two elements";
       return TDG_EINVAL;
     }
+  // boundary facets in ascending (element, opposite local vertex) order: the
+  // order of the per-facet kinds of tdg_mesh.bface_kind
+  T.bfacets.clear();
+  for (auto& kv : facets)
+    if (kv.second.size() == 1) T.bfacets.push_back(kv.second[0]);
+  std::sort(T.bfacets.begin(), T.bfacets.end());
+  std::map<std::pair<int, int>, int> bkind;
+  for (size_t i = 0; i < T.bfacets.size(); ++i) {
+    const int kd = m.bface_kind ? (int)m.bface_kind[i] : 0;
+    if (kd != 0 && kd != 1) {
+      err = "bface_kind entries must be 0 (Dirichlet) or 1 (Neumann)";
+      return TDG_EINVAL;
+    }
+    bkind[T.bfacets[i]] = kd;
+  }
   T.vb_ptr.assign(m.nv + 1, 0);
+  T.vn_ptr.assign(m.nv + 1, 0);
   T.vi_ptr.assign(m.nv + 1, 0);
   T.vb.clear();
+  T.vn.clear();
   T.vi.clear();
   for (int v = 0; v < m.nv; ++v) {
     std::vector<std::array<int, 4>> inter;
@@ -197,8 +210,9 @@ int build_topology(const tdg_mesh& m, const double* c, Topology& T, std::string&
         if (T.elems[(size_t)e * (n + 1) + k] == v) continue;
         const auto& sides = facets[facet_key(e, k)];
         if (sides.size() == 1) {
-          T.vb.push_back(e);
-          T.vb.push_back(k);
+          std::vector<int>& dst = bkind[{e, k}] == 0 ? T.vb : T.vn;
+          dst.push_back(e);
+          dst.push_back(k);
         } else if (sides[0].first == e && T.c[sides[0].first] != T.c[sides[1].first]) {
           inter.push_back({sides[0].first, sides[0].second, sides[1].first, sides[1].second});
         }
@@ -207,6 +221,7 @@ int build_topology(const tdg_mesh& m, const double* c, Topology& T, std::string&
     std::sort(inter.begin(), inter.end());
     for (auto& q : inter) T.vi.insert(T.vi.end(), q.begin(), q.end());
     T.vb_ptr[v + 1] = (int)T.vb.size() / 2;
+    T.vn_ptr[v + 1] = (int)T.vn.size() / 2;
     T.vi_ptr[v + 1] = (int)T.vi.size() / 4;
   }
   return TDG_OK;

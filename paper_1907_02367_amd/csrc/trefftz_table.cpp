@@ -340,6 +340,36 @@ Table build_table(int n, int p) {
   }
   tasks(T.expo, T.M, T.task1);
   T.ntask1 = (int)(T.task1.size() / kTaskInts);
+  // matrix-core evaluation (3+1D): every monomial of degree <= p is the product
+  // of an entry of the two-variable list (t, x1) and one of (x2, x3), both by
+  // degree; a tile of 16 (t, x1)-entries of smallest degree d needs the
+  // (x2, x3)-entries of degree <= p - d
+  if (n == 3) {
+    std::vector<std::array<int, 2>> lst;
+    std::map<std::array<int, 2>, int> pos;
+    for (int d = 0; d <= p; ++d)
+      for (int a = d; a >= 0; --a) {
+        pos[{a, d - a}] = (int)lst.size();
+        lst.push_back({a, d - a});
+      }
+    const int nl = (int)lst.size();
+    const int nat = (nl + 15) / 16;
+    if (nat <= 8) {
+      T.ev_nl = nl;
+      T.ev_nat = nat;
+      for (auto& e : lst) T.ev_ex.push_back(e[0] | e[1] << 8);
+      for (int I = 0; I < nat; ++I) {
+        const int dmin = lst[16 * I][0] + lst[16 * I][1];
+        const int need = (p - dmin + 1) * (p - dmin + 2) / 2;  // entries of degree <= p - dmin
+        T.ev_nks[I] = (need + 3) / 4;
+      }
+      for (int k = 0; k < T.M; ++k) {
+        const int* e = &T.expo[(size_t)k * (n + 1)];
+        const int a = pos.at({e[0], e[1]}), b = pos.at({e[2], e[3]});
+        T.ev_ab.push_back(a | b << 16);
+      }
+    }
+  }
   // transposed form: rows comp*M + monomial
   {
     std::vector<std::vector<std::pair<int, double>>> rows((size_t)ns * T.M);

@@ -46,6 +46,10 @@ _lib = None
 
 EXPORTS = {
     "tent_pitch": [ctypes.POINTER(_Mesh), ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)],
+    "tdg_boundary_facets": [ctypes.POINTER(_Mesh), ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p],
+    "trefftz_boundary_kinds": [ctypes.c_void_p, ctypes.c_void_p],
+    "trefftz_eval_u_error": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
     "tent_info": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
     "tent_export": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "tent_free": [ctypes.c_void_p],
@@ -209,11 +213,23 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
-def _mesh(coords, elems):
+def _mesh(coords, elems, bface_kind=None):
     coords = np.ascontiguousarray(coords, dtype=np.float64)
     elems = np.ascontiguousarray(elems, dtype=np.int32)
-    m = _Mesh(coords.shape[1], coords.shape[0], elems.shape[0], _ptr(coords), _ptr(elems), None)
-    return m, (coords, elems)
+    kinds = None if bface_kind is None else np.ascontiguousarray(bface_kind, dtype=np.int8)
+    m = _Mesh(coords.shape[1], coords.shape[0], elems.shape[0], _ptr(coords), _ptr(elems), _ptr(kinds))
+    return m, (coords, elems, kinds)
+
+
+def boundary_facets(coords, elems):
+    """(nbf, 2) int32: (element, local index of the opposite vertex) of every
+    boundary facet, in the order of the per-facet kinds (tdg_boundary_facets)."""
+    m, keep = _mesh(coords, elems)
+    nbf = ctypes.c_int64()
+    _check(lib().tdg_boundary_facets(ctypes.byref(m), ctypes.byref(nbf), None))
+    out = np.zeros((nbf.value, 2), np.int32)
+    _check(lib().tdg_boundary_facets(ctypes.byref(m), ctypes.byref(nbf), _ptr(out)))
+    return out
 
 
 def _stream(stream=None):
@@ -261,12 +277,13 @@ class Trefftz:
     """Solver context: trefftz_create + buffers (PyTorch) + trefftz_bind."""
 
     def __init__(self, coords, elems, c, tents: Tents, p_max: int, q: int = 0, alpha: float = 0.5,
-                 beta: float = 0.5, precision: int = 0, recover_U: int = 1, device=None, bind: bool = True):
+                 beta: float = 0.5, precision: int = 0, recover_U: int = 1, device=None, bind: bool = True,
+                 bface_kind=None):
         self.n = int(np.asarray(coords).shape[1])
         self.nv = int(np.asarray(coords).shape[0])
         self.ne = int(np.asarray(elems).shape[0])
         self.tents = tents
-        m, keep = _mesh(coords, elems)
+        m, keep = _mesh(coords, elems, bface_kind)
         c = np.ascontiguousarray(c, dtype=np.float64)
         opts = _Opts(int(p_max), int(q), float(alpha), float(beta), int(precision), 1, int(recover_U))
         h = ctypes.c_void_p()
@@ -300,6 +317,12 @@ class Trefftz:
         nb = ctypes.c_int64()
         _check(lib().trefftz_boundary_points(self._h, ctypes.byref(nb), _ptr(xt)))
         return xt
+
+    def boundary_kinds(self):
+        """Per boundary point: 0 on a Dirichlet face (g_D), 1 on a Neumann face (g_N)."""
+        k = np.zeros(max(self.nb, 1), np.int8)
+        _check(lib().trefftz_boundary_kinds(self._h, _ptr(k)))
+        return k[: self.nb]
 
     def bind(self, device=None):
         import torch
@@ -355,6 +378,13 @@ class Trefftz:
         s_ex = np.ascontiguousarray(sigma_ex, dtype=np.float64).reshape(-1)
         ea, er = ctypes.c_double(), ctypes.c_double()
         _check(lib().trefftz_eval_error(self._h, _ptr(v_ex), _ptr(s_ex), ctypes.byref(ea), ctypes.byref(er), _stream()))
+        return ea.value, er.value
+
+    def eval_u_error(self, U_ex):
+        U_ex = np.ascontiguousarray(U_ex, dtype=np.float64).reshape(-1)
+        assert U_ex.size == self.nq
+        ea, er = ctypes.c_double(), ctypes.c_double()
+        _check(lib().trefftz_eval_u_error(self._h, _ptr(U_ex), ctypes.byref(ea), ctypes.byref(er), _stream()))
         return ea.value, er.value
 
     def energy(self):

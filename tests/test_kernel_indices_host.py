@@ -141,3 +141,61 @@ def test_moment_phase_indices_stay_in_bounds_3d(p_max):
                 idx = t * 256 + ((lane >> 4) + 4 * r) * 16 + (lane & 15)
                 assert idx.max() < ntile * 256
     assert checked_tiles > 0
+
+
+@pytest.mark.parametrize("gram_mode", [0, 1])
+@pytest.mark.parametrize("p_max", [8, 3])
+def test_matrix_core_evaluation_indices_3d(p_max, gram_mode):
+    """The matrix-core evaluation of the solution at points (indicator and
+    write-back, 3+1D): every monomial of degree <= p is one (L, R) pair of the
+    two-variable list, each pair at most once; the k-steps of tile I cover the
+    R entries of degree <= p - (smallest degree of the tile); every LDS read of
+    the evaluation (dense coefficients, the 4 waves' point powers, the entry
+    list) lies inside the W1 region of the plan, and every read index is
+    inside its array."""
+    import ctypes
+    from paper_1907_02367_amd import tdg
+
+    pr = C.cfg5_cube_3d(m=3, p=p_max, variant="b", regions=1)
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, 0.05, 0.4 * 0.8 ** 4)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max, bind=False)
+    ctx.set_gram_mode(gram_mode)
+    L = tdg.lib()
+    f = L.tdg_debug_eval_tables
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    for p in range(1, p_max + 1):
+        info = np.zeros(12, np.int32)
+        assert f(ctx._h, p, info.ctypes.data, None, None) == 0
+        nl, nat, nks, M, w1 = int(info[0]), int(info[1]), info[2:10], int(info[10]), int(info[11])
+        assert nl == (p + 1) * (p + 2) // 2 and nat == (nl + 15) // 16
+        ab = np.zeros(M, np.int32)
+        ex = np.zeros(nl, np.int32)
+        assert f(ctx._h, p, info.ctypes.data, ab.ctypes.data, ex.ctypes.data) == 0
+        lst = [(int(e) & 255, int(e) >> 8) for e in ex]
+        assert lst == [(a, d - a) for d in range(p + 1) for a in range(d, -1, -1)]
+        pairs = [(int(x) & 0xFFFF, int(x) >> 16) for x in ab]
+        assert len(set(pairs)) == M
+        for a, b in pairs:
+            assert a < nl and b < nl and sum(lst[a]) + sum(lst[b]) <= p
+            # the pair is reached by the k-steps of a's tile
+            assert b < 4 * nks[a // 16]
+        ldb = nl | 1
+        nA16 = 16 * nat
+        dense = 5 * nA16 * ldb
+        P1 = p + 1
+        pww = 4 * 16 * 4 * P1
+        if dense + pww + (nl + 1) // 2 + 1 > w1:
+            continue  # the kernel keeps the VALU evaluation at this degree (its fit test)
+        # reads of eval16_mfma: coefficients, powers (pt <= 15, exponents <= p)
+        lane = np.arange(64)
+        for I in range(nat):
+            a = I * 16 + (lane & 15)
+            for ks in range(int(nks[I])):
+                b = ks * 4 + (lane >> 4)
+                ok = b < nl
+                idx = ((4 * nA16 + a) * ldb + b)[ok]
+                assert idx.max(initial=0) < dense
+                e = np.array([int(ex[bb]) for bb in b[ok]])
+                addr = (lane & 15)[ok] * 4 * P1 + 3 * P1 + (e >> 8)
+                assert addr.max(initial=0) < 16 * 4 * P1

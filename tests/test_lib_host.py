@@ -112,13 +112,63 @@ def test_errors_are_reported_not_raised_across_the_abi():
         with pytest.raises(tdg.TdgError) as ei:
             tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p, bind=False)
         assert ei.value.name == "TDG_EINVAL"
-    # recovery of U: only the documented values are accepted
+    # recovery of U: only the documented values are accepted; the paper's form
+    # (2) only with the FP64 quadrature Gram
     for ru in (-1, 3, 7):
         with pytest.raises(tdg.TdgError) as ei:
             tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, recover_U=ru, bind=False)
         assert ei.value.name == "TDG_EINVAL"
-    for ru in (0, 1):
+    for ru in (0, 1, 2):
         tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, recover_U=ru, bind=False)
+    with pytest.raises(tdg.TdgError) as ei:
+        tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, recover_U=2, precision=1, bind=False)
+    assert ei.value.name == "TDG_EINVAL"
+    ctx2 = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, recover_U=2, bind=False)
+    with pytest.raises(tdg.TdgError) as ei:
+        ctx2.set_gram_mode(1)
+    assert ei.value.name == "TDG_EINVAL"
+    # boundary-facet kinds must be 0 or 1
+    nbf = len(tdg.boundary_facets(pr.coords, pr.elems))
+    bad = np.zeros(nbf, np.int8)
+    bad[0] = 2
+    with pytest.raises(tdg.TdgError) as ei:
+        tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, bface_kind=bad, bind=False)
+    assert ei.value.name == "TDG_EINVAL"
+
+
+@pytest.mark.parametrize("builder", [lambda: C.cfg1_standing_1d(n_elems=5), lambda: C.cfg2_plane_2d(m=6),
+                                     lambda: C.cfg5_cube_3d(m=2, variant="b", regions=1)])
+def test_boundary_facets_and_neumann_points(builder):
+    """The library lists the boundary facets in the oracle's order (ascending
+    (element, opposite local vertex)), and with Neumann facets the boundary
+    points of each tent are its Dirichlet faces' then its Neumann faces', each
+    point on a facet of its kind."""
+    from oracle.topology import Topology
+    from paper_1907_02367_amd import tdg
+
+    pr = builder()
+    bf = tdg.boundary_facets(pr.coords, pr.elems)
+    topo = Topology(pr.coords, pr.elems, pr.c)
+    assert [tuple(x) for x in bf.tolist()] == [tuple(map(int, x)) for x in topo.boundary_facets()]
+    # Neumann on the facets whose centroid has x_0 < 1/2
+    cen = np.array([pr.coords[[v for j, v in enumerate(pr.elems[e]) if j != k]].mean(axis=0) for e, k in bf])
+    kinds = (cen[:, 0] < 0.5).astype(np.int8)
+    assert 0 < kinds.sum() < len(kinds)
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, 0.2, pr.gamma)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=2, bind=False, bface_kind=kinds)
+    ctx_d = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=2, bind=False)
+    assert ctx.nb == ctx_d.nb  # the same faces, split by kind
+    xt = ctx.boundary_points()
+    bk = ctx.boundary_kinds()
+    assert set(np.unique(bk)) == {0, 1}
+    # every point lies within the x_0-range of the facets of its kind
+    x0 = xt[:, 0]
+    vx = np.array([[pr.coords[v, 0] for j, v in enumerate(pr.elems[e]) if j != k] for e, k in bf])
+    for kd in (0, 1):
+        sel = vx[kinds == kd]
+        assert (x0[bk == kd] <= sel.max() + 1e-12).all() and (x0[bk == kd] >= sel.min() - 1e-12).all()
+    if pr.n == 1:
+        assert np.allclose(x0[bk == 1], 0.0) and np.allclose(x0[bk == 0], 1.0)
 
 
 def test_gram_modes_and_shapes_are_planned_on_the_host():
