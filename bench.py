@@ -295,7 +295,7 @@ def bench_cube_3d(args):
         },
         "roofline": {
             "bound": "alu", "achieved": r["achieved_alg"] / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": r["achieved_alg"] / FP64_PEAK, "traffic": None,
+            "frac": r["achieved_alg"] / FP64_PEAK, "traffic": measured_traffic(f"cube_3d_{main_path}"),
             "kernel": "tent_layer_kernel<3,1,false,true> (moment Gram, FP64)",
             "count": "quadrature-form operation count of eq. 4.1 per tent at its degree (the survey's formula)",
             "achieved_executed": r["achieved_exec"] / 1e12, "frac_executed": r["achieved_exec"] / FP64_PEAK,

@@ -213,6 +213,28 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         L.total = off;
         if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) {
           plan_lu_block(L, n);
+          // lower degrees: a larger moment chunk in the free tail of W1
+          const long long w1_have = (long long)L.off_fg - L.off_W1;
+          for (int p = 0; p <= kMaxP; ++p) {
+            L.mpch[p] = L.pch[p];
+            L.moff[p] = -1;
+          }
+          if (n == 3)
+            for (int p = 2; p <= pmax; ++p) {
+              const Table& tb = X->tabs[p];
+              if (!tb.mt_ntile) continue;
+              const long long used = ((long long)(n + 1) * tb.M2 + (long long)(n + 1) * tb.M1 + tb.M + 3) & ~3LL;
+              for (int cand : {64, 32}) {
+                if (cand <= L.pch[p]) break;
+                const long long need = (long long)cand * (2 * (n + 1) + 1 + (n + 2)) +
+                                       (long long)cand * (n + 1) * ((2 * p - 1) + (p + 1));
+                if (used + need <= w1_have) {
+                  L.mpch[p] = cand;
+                  L.moff[p] = (int)used;
+                  break;
+                }
+              }
+            }
           return TDG_OK;
         }
       }
@@ -282,6 +304,10 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         L.total = off;
         if ((size_t)L.total * sizeof(double) + 1024 <= 160 * 1024) {
           plan_lu_block(L, n);
+          for (int p = 0; p <= kMaxP; ++p) {
+            L.mpch[p] = L.pch[p];
+            L.moff[p] = -1;
+          }
           return TDG_OK;
         }
         // shrink the largest lower-degree chunk, if any is above the p_max chunk
@@ -302,6 +328,8 @@ int upload_tabd(tdg_ctx* X, hipStream_t stream, bool async) {
     X->tabd[p].pch = X->lp.pch[p];
     X->tabd[p].nwp = X->lp.nwp[p];
     X->tabd[p].pci = X->lp.pci[p];
+    X->tabd[p].mpch = X->lp.mpch[p];
+    X->tabd[p].moff = X->lp.moff[p];
   }
   void* dst = (double*)X->dev[TDG_BUF_F64] + X->o_tabd;
   const size_t bytes = sizeof(TableDesc) * (kMaxP + 1);
@@ -1127,7 +1155,8 @@ int tdg_debug_moment_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t*
 }
 
 // Internal (host-side index replay in the tests): the matrix-core evaluation
-// tables of degree p.  info[12] = {ev_nl, ev_nat, ev_nks[0..7], M, W1 doubles}.
+// tables of degree p and the moment-phase chunk.  info[14] = {ev_nl, ev_nat,
+// ev_nks[0..7], M, W1 doubles, mpch[p], moff[p] (-1: the default regions)}.
 int tdg_debug_eval_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t* ev_ab, int32_t* ev_ex) {
   if (!X || !info) return fail(TDG_EINVAL, "NULL argument");
   if (p < 1 || p > X->opts.p_max) return fail(TDG_EINVAL, "p out of range");
@@ -1137,6 +1166,8 @@ int tdg_debug_eval_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t* e
   for (int i = 0; i < 8; ++i) info[2 + i] = t.ev_nks[i];
   info[10] = t.M;
   info[11] = X->lp.off_fg - X->lp.off_W1;
+  info[12] = X->lp.mpch[p];
+  info[13] = X->lp.moff[p];
   if (ev_ab) std::copy(t.ev_ab.begin(), t.ev_ab.end(), ev_ab);
   if (ev_ex) std::copy(t.ev_ex.begin(), t.ev_ex.end(), ev_ex);
   return TDG_OK;

@@ -45,6 +45,7 @@ constexpr long long kNoAllocMaxSamples = 8192;
 struct TableDesc {
   int p, NW, M, M1, M2, fo_nnz, u_nnz, ue_n, tr_n;
   int pch, nwp, pci;  // execution plan at this degree: points per chunk, operand stride, face chunk
+  int mpch, moff;     // 3+1D moment phase: points per chunk and (>= 0) its regions' offset in W1
   const int* expo2;  // M2*(n+1) exponents of the moment monomials (degree <= 2p-2)
   const int* K2;     // M1*M1: moment index of the product of monomials k, l < M1
   const int* task2;  // ntask2 moment tasks over the moment monomials (degree <= 2p-2)
@@ -162,6 +163,10 @@ struct LdsPlan {
   int moment;    // 1: Gram and right-hand sides from point moments of the monomials
   int pci[kMaxP + 1];  // points per chunk of the interface faces at each degree
   int lu_nb;     // panel width of the blocked LU of a system in global memory (0: unblocked)
+  // 3+1D moment phase at degree p: a larger chunk (mpch points) whose point and
+  // power regions sit in the part of W1 the degree's moments leave free (moff,
+  // doubles from W1), or moff = -1: the chunk regions of p_max
+  int mpch[kMaxP + 1], moff[kMaxP + 1];
   int off_A, off_x, off_tab, off_el, off_misc, off_pt, off_pow, off_mono, off_W1, off_fg, off_AF, off_vec, total;
 };
 
@@ -169,6 +174,9 @@ struct LdsPlan {
 // coefficients of the n+2 fields over (L entry, R entry) pairs, the powers of
 // 16 points per wave (4 waves, n+1 variables, exponents 0..p), the entry list
 constexpr int ev_ldb(int nl) { return nl | 1; }
+// k-steps of 4 entries held in registers by the evaluation: ceil(66 / 4) covers
+// the two-variable list of degree 10
+constexpr int kEvalMaxSteps = 17;
 constexpr long long ev_doubles(int p, int nl) {
   return 5LL * (16 * ((nl + 15) / 16)) * ev_ldb(nl) + 4LL * 16 * 4 * (p + 1) + (nl + 1) / 2 + 1;
 }

@@ -506,31 +506,49 @@ __device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, c
       const int amax = dirichlet ? 0 : NS;
       for (int a = 0; a <= amax; ++a) {
         const int row = i * (NS + 1) + a;
-        for (int e = fo_ptr[row]; e < fo_ptr[row + 1]; ++e) {
-          const int k = fo_idx[e];
-          const double al = fo_coef[e];
-          const int* K2r = K2 + k * M1;
+        const int e1 = fo_ptr[row + 1];
+        // terms in groups of four: their product-index loads (global) are issued
+        // together; a missing term enters with coefficient 0 at index 0 (adding
+        // zero leaves every sum unchanged, the order of the terms is kept)
+        for (int e = fo_ptr[row]; e < e1; e += 4) {
+          int kk[4];
+          double al[4];
 #pragma unroll
-          for (int s = 0; s < 2; ++s) {
-            const int l = l0 + tid + s * (int)blockDim.x;
-            if (l < M1) {
-              const int b2 = K2r[l];
-              if (dirichlet) {
-                z[s][0] += ca * al * NU[b2];
+          for (int u = 0; u < 4; ++u) {
+            kk[u] = e + u < e1 ? fo_idx[e + u] : 0;
+            al[u] = e + u < e1 ? fo_coef[e + u] : 0.0;
+          }
+          int b2[4][2];
 #pragma unroll
-                for (int d = 0; d < NS; ++d) z[s][1 + d] += cr * al * NU[(1 + d) * M2 + b2];
-              } else if (a == 0) {
-                z[s][0] += al * NU[b2];
+          for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int d = 0; d < NS; ++d) z[s][1 + d] -= cr * al * NU[(1 + d) * M2 + b2];
-              } else {
+            for (int s = 0; s < 2; ++s) {
+              const int l = l0 + tid + s * (int)blockDim.x;
+              b2[u][s] = l < M1 ? K2[kk[u] * M1 + l] : 0;
+            }
 #pragma unroll
-                for (int c = 1; c <= NS; ++c)
-                  if (c == a) z[s][c] += al * NU[b2];
-                z[s][0] -= cr * al * NU[a * M2 + b2];
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+              const int l = l0 + tid + s * (int)blockDim.x;
+              if (l < M1) {
+                const int b = b2[u][s];
+                if (dirichlet) {
+                  z[s][0] += ca * al[u] * NU[b];
+#pragma unroll
+                  for (int d = 0; d < NS; ++d) z[s][1 + d] += cr * al[u] * NU[(1 + d) * M2 + b];
+                } else if (a == 0) {
+                  z[s][0] += al[u] * NU[b];
+#pragma unroll
+                  for (int d = 0; d < NS; ++d) z[s][1 + d] -= cr * al[u] * NU[(1 + d) * M2 + b];
+                } else {
+#pragma unroll
+                  for (int c = 1; c <= NS; ++c)
+                    if (c == a) z[s][c] += al[u] * NU[b];
+                  z[s][0] -= cr * al[u] * NU[a * M2 + b];
+                }
               }
             }
-          }
         }
       }
 #pragma unroll
@@ -544,10 +562,28 @@ __device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, c
     __syncthreads();
     const int jmax = dirichlet ? NW - 1 : i;
     for (int j = tid; j <= jmax; j += blockDim.x) {
+      // the terms of function j (components b = 0..NS, consecutive in the table)
+      // eight at a time: their table loads are issued together; the sum keeps
+      // the term order
+      int bnd[NS + 2];
+#pragma unroll
+      for (int b = 0; b <= NS + 1; ++b) bnd[b] = fo_ptr[j * (NS + 1) + b];
       double acc = 0.0;
-      for (int b = 0; b <= NS; ++b) {
-        const int row = j * (NS + 1) + b;
-        for (int e = fo_ptr[row]; e < fo_ptr[row + 1]; ++e) acc += fo_coef[e] * Z[b * M1 + fo_idx[e]];
+      for (int e = bnd[0]; e < bnd[NS + 1]; e += 8) {
+        int ix[8];
+        double cf[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          ix[u] = e + u < bnd[NS + 1] ? fo_idx[e + u] : 0;
+          cf[u] = e + u < bnd[NS + 1] ? fo_coef[e + u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          int b = 0;
+#pragma unroll
+          for (int c = 1; c <= NS; ++c) b += e + u >= bnd[c] ? 1 : 0;
+          if (e + u < bnd[NS + 1]) acc += cf[u] * Z[b * M1 + ix[u]];
+        }
       }
       A[(long long)(row0 + i) * lda + row0 + j] += acc;
       if (!dirichlet && j != i) A[(long long)(row0 + j) * lda + row0 + i] += acc;
@@ -796,30 +832,51 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
     acc[s] = d4{0.0, 0.0, 0.0, 0.0};
   }
   __syncthreads();
-  for (int ei = 0; ei < nel; ++ei) {
+  // chunks of at most PCH points of one element, flattened: chunk c covers
+  // element gel[c / cpe], points (c % cpe) PCH .. ; thread pt < PCH keeps the
+  // global data of its point of the next chunk in registers (state, reference
+  // coordinates, weight), loaded while the current chunk is processed
+  const int cpe = (Q + PCH - 1) / PCH;
+  const int nchunk = nel * cpe;
+  double g_st[NS + 2], g_lam[NS + 1], g_w = 0.0;
+  auto fetch = [&](int c) {
+    const int pt = tid;
+    if (c < nchunk && pt < PCH) {
+      const int q = (c % cpe) * PCH + pt;
+      if (q < Q) {
+        const double* Rn = EL + gel[c / cpe] * ELS;
+        const double* st = state + (size_t)(int)Rn[El<NS>::E] * (NS + 2) * Q;
+#pragma unroll
+        for (int k = 0; k < NS + 2; ++k) g_st[k] = st[k * Q + q];
+#pragma unroll
+        for (int k = 0; k <= NS; ++k) g_lam[k] = lam_ref[(size_t)q * (NS + 1) + k];
+        g_w = w_ref[q];
+      }
+    }
+  };
+  fetch(0);
+  for (int cc = 0; cc < nchunk; ++cc) {
+    const int ei = cc / cpe, q0 = (cc % cpe) * PCH;
     const double* R = EL + gel[ei] * ELS;
-    for (int q0 = 0; q0 < Q; q0 += PCH) {
+    {
       const int nc = min(PCH, Q - q0);
-      for (int pt = tid; pt < nc; pt += blockDim.x) {
-        const int q = q0 + pt;
+      if (tid < nc) {
+        const int pt = tid;
         const int lV = (int)R[El<NS>::LV];
-        const int e = (int)R[El<NS>::E];
-        const double* lam = lam_ref + (size_t)q * (NS + 1);
         double xt[NS], pho = 0.0;
         for (int d = 0; d < NS; ++d) xt[d] = 0.0;
         for (int k = 0; k <= NS; ++k) {
-          pho += lam[k] * R[El<NS>::TAU + k];
-          for (int d = 0; d < NS; ++d) xt[d] += lam[k] * R[El<NS>::X + k * NS + d];
+          pho += g_lam[k] * R[El<NS>::TAU + k];
+          for (int d = 0; d < NS; ++d) xt[d] += g_lam[k] * R[El<NS>::X + k * NS + d];
         }
-        const double phi = pho + lam[lV] * dt;
-        const double w = w_ref[q] * R[El<NS>::DET];
-        const double* st = state + (size_t)e * (NS + 2) * Q;
-        const double vb = st[q];
+        const double phi = pho + g_lam[lV] * dt;
+        const double w = g_w * R[El<NS>::DET];
+        const double vb = g_st[0];
         double sg = 0.0;
-        for (int d = 0; d < NS; ++d) sg += st[(1 + d) * Q + q] * R[El<NS>::GOLD + d];
+        for (int d = 0; d < NS; ++d) sg += g_st[1 + d] * R[El<NS>::GOLD + d];
         PD[pt * (NS + 2)] = w * (ic2 * vb - sg);
-        for (int d = 0; d < NS; ++d) PD[pt * (NS + 2) + 1 + d] = w * (st[(1 + d) * Q + q] - vb * R[El<NS>::GOLD + d]);
-        PD[pt * (NS + 2) + NS + 1] = w * st[(NS + 1) * Q + q];
+        for (int d = 0; d < NS; ++d) PD[pt * (NS + 2) + 1 + d] = w * (g_st[1 + d] - vb * R[El<NS>::GOLD + d]);
+        PD[pt * (NS + 2) + NS + 1] = w * g_st[NS + 1];
         PV[pt * (NS + 1)] = cr * (phi - tmid) / hr;
         PV[(PCH + pt) * (NS + 1)] = cr * (pho - tmid) / hr;
         for (int d = 0; d < NS; ++d) {
@@ -830,6 +887,7 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         PW[pt] = w;
       }
       __syncthreads();
+      fetch(cc + 1);  // the next chunk's global data, in flight during this chunk
       for (int i = tid; i < nc * (NS + 1); i += blockDim.x) {
         const int pt = i / (NS + 1), v = i % (NS + 1);
         double x = PV[pt * (NS + 1) + v], a = 1.0;
@@ -847,25 +905,27 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         }
       }
       __syncthreads();
-      // top moment tiles of this chunk
+      // top moment tiles of this chunk.  The operand loads of all slots are issued
+      // together: every index lies in this point's power row (a slot past the
+      // wave's tiles has exponents 0), and points past nc are masked by a select
+      // after the loads (their LDS words may hold anything)
       const int nks = (nc + 3) >> 2;
       for (int ks = 0; ks < nks; ++ks) {
         const int pt = ks * 4 + (lane >> 4);
         const bool ok = pt < nc;
         const double* pw = POWT + pt * (NS + 1) * E2;
-        const double w = ok ? PW[pt] : 0.0;
+        const double w = PW[pt];
+        double a[kMomTileSlots], b[kMomTileSlots];
 #pragma unroll
         for (int s = 0; s < kMomTileSlots; ++s) {
-          if (wave + 4 * s < ntile) {
-            const unsigned ex = tex[s];
-            double a = 0.0, b = 0.0;
-            if (ok) {
-              a = w * pw[ex & 31u] * pw[E2 + ((ex >> 5) & 31u)];
-              b = pw[2 * E2 + ((ex >> 10) & 31u)] * pw[3 * E2 + ((ex >> 15) & 31u)];
-            }
-            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
-          }
+          const unsigned ex = tex[s];
+          a[s] = w * pw[ex & 31u] * pw[E2 + ((ex >> 5) & 31u)];
+          b[s] = pw[2 * E2 + ((ex >> 10) & 31u)] * pw[3 * E2 + ((ex >> 15) & 31u)];
         }
+#pragma unroll
+        for (int s = 0; s < kMomTileSlots; ++s)
+          if (wave + 4 * s < ntile)
+            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? a[s] : 0.0, ok ? b[s] : 0.0, acc[s], 0, 0, 0);
       }
       // bottom moments (monomials of degree <= p), VALU tasks
 #pragma unroll
@@ -920,26 +980,28 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         }
       __syncthreads();
     }
-    // fold the element's tiles (each moment index belongs to one tile entry, so
-    // no two lanes or waves write the same word)
-    double g[NS];
+    // after the element's last chunk: fold its tiles (each moment index belongs
+    // to one tile entry, so no two lanes or waves write the same word)
+    if (cc % cpe == cpe - 1) {
+      double g[NS];
 #pragma unroll
-    for (int d = 0; d < NS; ++d) g[d] = R[El<NS>::GNEW + d];
+      for (int d = 0; d < NS; ++d) g[d] = R[El<NS>::GNEW + d];
 #pragma unroll
-    for (int s = 0; s < kMomTileSlots; ++s) {
-      const int t = wave + 4 * s;
-      if (t < ntile) {
+      for (int s = 0; s < kMomTileSlots; ++s) {
+        const int t = wave + 4 * s;
+        if (t < ntile) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int b = mt_map[t * 256 + ((lane >> 4) + 4 * r) * 16 + (lane & 15)];
-          if (b >= 0) {
-            const double c = acc[s][r];
-            NU[b] += c;
+          for (int r = 0; r < 4; ++r) {
+            const int b = mt_map[t * 256 + ((lane >> 4) + 4 * r) * 16 + (lane & 15)];
+            if (b >= 0) {
+              const double c = acc[s][r];
+              NU[b] += c;
 #pragma unroll
-            for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += g[d] * c;
+              for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += g[d] * c;
+            }
           }
+          acc[s] = d4{0.0, 0.0, 0.0, 0.0};
         }
-        acc[s] = d4{0.0, 0.0, 0.0, 0.0};
       }
     }
   }
@@ -1001,12 +1063,29 @@ __device__ inline void eval_runs(const Tab& T, const int* runs, const double* va
 template <int NC>
 __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl, int nat, const int* nks,
                                    const int* EX, const double* PWW, int P1, double (&val)[NC][4]) {
+  constexpr int KMAX = kEvalMaxSteps;
   const int lane = threadIdx.x & 63;
   const int pi = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
     for (int r = 0; r < 4; ++r) val[c][r] = 0.0;
+  // the A operands R_b(point pi), b = 4 ks + kq, once for every field and tile
+  // (tile 0 needs the most steps)
+  const int nk0 = nks[0];
+  double rv[KMAX];
+  {
+    const double* pw = PWW + pi * 4 * P1;
+#pragma unroll
+    for (int ks = 0; ks < KMAX; ++ks) {
+      const int b = ks * 4 + kq;
+      rv[ks] = 0.0;
+      if (ks < nk0 && b < nl) {
+        const int eb = EX[b];
+        rv[ks] = pw[2 * P1 + (eb & 255)] * pw[3 * P1 + (eb >> 8)];
+      }
+    }
+  }
   for (int I = 0; I < nat; ++I) {
     const int a = I * 16 + pi;
     const int ea = a < nl ? EX[a] : 0;
@@ -1017,23 +1096,25 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
       La[r] = a < nl ? pw[ea & 255] * pw[P1 + (ea >> 8)] : 0.0;
     }
     const int nk = nks[I];
+    d4 acc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-      for (int ks = 0; ks < nk; ++ks) {
+    for (int c = 0; c < NC; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+    // the fields' chains interleaved (independent accumulators)
+#pragma unroll
+    for (int ks = 0; ks < KMAX; ++ks) {
+      if (ks < nk) {
         const int b = ks * 4 + kq;
-        double av = 0.0, bv = 0.0;
-        if (b < nl) {
-          const int eb = EX[b];
-          const double* pw = PWW + pi * 4 * P1;
-          av = pw[2 * P1 + (eb & 255)] * pw[3 * P1 + (eb >> 8)];
-          bv = CMd[((long long)c * nA16 + a) * ldb + b];
-        }
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-      }
+        double bv[NC];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) val[c][r] += acc[r] * La[r];
+        for (int c = 0; c < NC; ++c) bv[c] = b < nl ? CMd[((long long)c * nA16 + a) * ldb + b] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[ks], bv[c], acc[c], 0, 0, 0);
+      }
     }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) val[c][r] += acc[c][r] * La[r];
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c)
@@ -1348,9 +1429,20 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
       bool done_mt = false;
       if constexpr (NS == 3) {
         if (Dp.mt_ntile > 0) {
+          // a lower degree may take a larger chunk in the free tail of W1
+          int mpch = PCH;
+          double *mPV = PV, *mPW = PW, *mPD = PD, *mPOWT = POWT, *mPOWB = POWB;
+          if (Dp.moff >= 0) {
+            mpch = Dp.mpch;
+            mPV = W1 + Dp.moff;
+            mPW = mPV + 2 * mpch * (NS + 1);
+            mPD = mPW + mpch;
+            mPOWT = mPD + mpch * (NS + 2);
+            mPOWB = mPOWT + mpch * (NS + 1) * E2;
+          }
           moment_points_mt<NS>(P.lam_ref, P.w_ref, P.state, Q, EL, ELS, s_gel + s_goff[r], s_goff[r + 1] - s_goff[r],
-                               XV, cr, hr, tmid, dt, p, PCH, M1, M2, Mm, T.task1, T.ntask1, Dp.mt_ntile, Dp.mt_ex,
-                               Dp.mt_map, NU, BV, BU, PV, PW, PD, POWT, POWB, A00 + r, r0 + r);
+                               XV, cr, hr, tmid, dt, p, mpch, M1, M2, Mm, T.task1, T.ntask1, Dp.mt_ntile, Dp.mt_ex,
+                               Dp.mt_map, NU, BV, BU, mPV, mPW, mPD, mPOWT, mPOWB, A00 + r, r0 + r);
           done_mt = true;
         }
       }

@@ -354,7 +354,7 @@ Table build_table(int n, int p) {
       }
     const int nl = (int)lst.size();
     const int nat = (nl + 15) / 16;
-    if (nat <= 8) {
+    if (nat <= 8 && (nl + 3) / 4 <= kEvalMaxSteps) {
       T.ev_nl = nl;
       T.ev_nat = nat;
       for (auto& e : lst) T.ev_ex.push_back(e[0] | e[1] << 8);

@@ -126,10 +126,10 @@ def test_moment_phase_indices_stay_in_bounds_3d(p_max):
                 assert pt.max() < PCH  # inside the chunk's regions even for padded points
                 for w in range(4):
                     for s in range(K_MOM_SLOTS):
+                        # every slot's operands are loaded (a slot past the wave's
+                        # tiles has exponents 0), only valid slots reach the MFMA
                         t = w + 4 * s
-                        if t >= ntile:
-                            continue
-                        e = exps[t, lane % 16]
+                        e = exps[t, lane % 16] if t < ntile else np.zeros(64, np.int64)
                         base = pt * (n + 1) * E2
                         for v, sh in enumerate((0, 5, 10, 15)):
                             addr = base + v * E2 + ((e >> sh) & 31)
@@ -165,9 +165,18 @@ def test_matrix_core_evaluation_indices_3d(p_max, gram_mode):
     f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     f.restype = ctypes.c_int
     for p in range(1, p_max + 1):
-        info = np.zeros(12, np.int32)
+        info = np.zeros(14, np.int32)
         assert f(ctx._h, p, info.ctypes.data, None, None) == 0
         nl, nat, nks, M, w1 = int(info[0]), int(info[1]), info[2:10], int(info[10]), int(info[11])
+        mpch, moff = int(info[12]), int(info[13])
+        if moff >= 0:
+            # the larger moment chunk of this degree sits behind its moments in W1:
+            # points (2 (n+1) + 1 + (n+2) doubles each) and powers (E2 + p + 1 per
+            # variable); the moments themselves take (n+1) M2 + (n+1) M1 + M
+            assert gram_mode == 1 and mpch % 4 == 0 and mpch in (32, 64)
+            M1, M2 = comb(p - 1 + 4, 4), comb(2 * p - 2 + 4, 4)
+            assert moff >= 4 * M2 + 4 * M1 + M
+            assert moff + mpch * (8 + 1 + 5) + mpch * 4 * ((2 * p - 1) + (p + 1)) <= w1
         assert nl == (p + 1) * (p + 2) // 2 and nat == (nl + 15) // 16
         ab = np.zeros(M, np.int32)
         ex = np.zeros(nl, np.int32)
