@@ -887,7 +887,6 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         PW[pt] = w;
       }
       __syncthreads();
-      fetch(cc + 1);  // the next chunk's global data, in flight during this chunk
       for (int i = tid; i < nc * (NS + 1); i += blockDim.x) {
         const int pt = i / (NS + 1), v = i % (NS + 1);
         double x = PV[pt * (NS + 1) + v], a = 1.0;
@@ -905,6 +904,9 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         }
       }
       __syncthreads();
+      // the next chunk's global data, in flight during the moments of this chunk
+      // (no barrier between here and the chunk's end)
+      fetch(cc + 1);
       // top moment tiles of this chunk.  The operand loads of all slots are issued
       // together: every index lies in this point's power row (a slot past the
       // wave's tiles has exponents 0), and points past nc are masked by a select
@@ -943,7 +945,7 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
 #pragma unroll
           for (int q = 0; q <= NS; ++q) bv[c][q] = 0.0;
         }
-#pragma unroll 1
+#pragma unroll 4
         for (int pt = 0; pt < nc; ++pt) {
           const double* pw = POWB + pt * (NS + 1) * (p + 1);
           double pre = pw[e[0]];
