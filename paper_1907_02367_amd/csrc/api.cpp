@@ -708,6 +708,7 @@ int trefftz_bind(tdg_ctx* X, void* const dev_ptrs[TDG_NBUF], tdg_stream stream) 
     D.ev_nl = tb.ev_nl;
     D.ev_nat = tb.ev_nat;
     for (int i = 0; i < 8; ++i) D.ev_nks[i] = tb.ev_nks[i];
+    for (int i = 0; i < 8; ++i) D.ev_nkv[i] = tb.ev_nkv[i];
     D.ev_ab = I + o.ev_ab;
     D.ev_ex = I + o.ev_ex;
     D.fo_nnz = (int)tb.fo_idx.size();
@@ -1155,8 +1156,9 @@ int tdg_debug_moment_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t*
 }
 
 // Internal (host-side index replay in the tests): the matrix-core evaluation
-// tables of degree p and the moment-phase chunk.  info[14] = {ev_nl, ev_nat,
-// ev_nks[0..7], M, W1 doubles, mpch[p], moff[p] (-1: the default regions)}.
+// tables of degree p and the moment-phase chunk.  info[22] = {ev_nl, ev_nat,
+// ev_nks[0..7], M, W1 doubles, mpch[p], moff[p] (-1: the default regions),
+// ev_nkv[0..7]}.
 int tdg_debug_eval_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t* ev_ab, int32_t* ev_ex) {
   if (!X || !info) return fail(TDG_EINVAL, "NULL argument");
   if (p < 1 || p > X->opts.p_max) return fail(TDG_EINVAL, "p out of range");
@@ -1168,6 +1170,7 @@ int tdg_debug_eval_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t* e
   info[11] = X->lp.off_fg - X->lp.off_W1;
   info[12] = X->lp.mpch[p];
   info[13] = X->lp.moff[p];
+  for (int i = 0; i < 8; ++i) info[14 + i] = t.ev_nkv[i];
   if (ev_ab) std::copy(t.ev_ab.begin(), t.ev_ab.end(), ev_ab);
   if (ev_ex) std::copy(t.ev_ex.begin(), t.ev_ex.end(), ev_ex);
   return TDG_OK;

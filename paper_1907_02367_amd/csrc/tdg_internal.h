@@ -63,7 +63,8 @@ struct TableDesc {
   // e_first | e_second << 8 of entry i of the (shared) two-variable list of
   // degree <= p (ev_nl entries, by degree); ev_nat tiles of 16 L entries, tile I
   // needs ev_nks[I] steps of 4 R entries; ev_nl = 0: not used at this degree
-  int ev_nl, ev_nat, ev_nks[8];
+  // (ev_nkv[I]: the same for v and sigma, whose degree is at most p - 1)
+  int ev_nl, ev_nat, ev_nks[8], ev_nkv[8];
   const int* ev_ab;
   const int* ev_ex;
   // entry form: entries of basis function j+1 are ue_ptr[j]..ue_ptr[j+1]-1; entry e
@@ -237,6 +238,7 @@ struct Table {
   int mt_ntile = 0;                // matrix-core top-moment tiles (see TableDesc)
   std::vector<int> mt_ex, mt_map;
   int ev_nl = 0, ev_nat = 0, ev_nks[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // matrix-core evaluation (see TableDesc)
+  int ev_nkv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<int> ev_ab, ev_ex;
   std::vector<int> parent, var;
   std::vector<int> expo;  // M*(n+1): k, alpha_1..alpha_n

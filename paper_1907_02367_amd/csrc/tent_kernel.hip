@@ -28,6 +28,8 @@
 //   6. (v, sigma, U) at the top points overwrite the stored values; tau_V = t_top.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "tdg_internal.h"
 
 namespace tdg {
@@ -56,6 +58,12 @@ struct El {
 
 __device__ inline void atomic_max_nonneg(double* addr, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+// load from global memory through a global (not flat) address: flat loads also
+// count against the LDS wait counter, so every later LDS wait would wait for them
+__device__ inline double gload(const double* p) {
+  return *(const __attribute__((address_space(1))) double*)p;
 }
 
 // ordering of LDS accesses inside one wave (no workgroup barrier needed)
@@ -603,11 +611,15 @@ template <int NSLOT>
 struct TaskRegs {
   unsigned w0[NSLOT], w1[NSLOT], w2[NSLOT];
 };
+// slot s of a thread holds task t0 + s * stride (by default the thread index
+// and the block size)
 template <int NSLOT>
-__device__ inline void load_tasks(const int* task, int ntask, TaskRegs<NSLOT>& R) {
+__device__ inline void load_tasks(const int* task, int ntask, TaskRegs<NSLOT>& R, int t0 = -1, int stride = 0) {
+  if (t0 < 0) t0 = threadIdx.x;
+  if (stride <= 0) stride = blockDim.x;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
-    const int t = threadIdx.x + s * blockDim.x;
+    const int t = t0 + s * stride;
     R.w0[s] = t < ntask ? (unsigned)task[t * kTaskInts] : 0u;
     R.w1[s] = t < ntask ? (unsigned)task[t * kTaskInts + 1] : 0xFFFFFFFFu;
     R.w2[s] = t < ntask ? (unsigned)task[t * kTaskInts + 2] : 0xFFFFFFFFu;
@@ -806,9 +818,13 @@ __device__ inline void moment_points(const double* lam_ref, const double* w_ref,
 // step).  grad phi_new is constant on an element, so after its last chunk
 //   nu[b] += C_e[b],  nu_d[b] += g_d C_e[b]   (b = mt_map of the tile entry)
 // and the tiles restart from zero.  The bottom moments and the recovery-row
-// sums are those of moment_points (VALU tasks).  Chunks hold at most PCH points
-// of one element (PCH a multiple of 4: every k-step reads inside the chunk's
-// regions; points past the chunk enter with zero operands).
+// sums are those of moment_points (VALU tasks); with at most 64 (128) tasks the
+// tasks are repeated in 4 (2) groups of waves, group s taking the points
+// s, s + nsplit, ... of every chunk, so that all waves share them.  The first
+// task slot of a thread sums over all chunks in registers; the groups add
+// their sums in group order after the last chunk.  Chunks hold at most PCH
+// points of one element (PCH a multiple of 4: every k-step reads inside the
+// chunk's regions; points past the chunk enter with zero operands).
 template <int NS>
 __device__ inline void moment_points_mt(const double* lam_ref, const double* w_ref, const double* state, int Q,
                                         const double* EL, int ELS, const int* gel, int nel, const double* XV,
@@ -816,13 +832,66 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
                                         int Mm, const int* task1, int ntask1, int ntile, const int* mt_ex,
                                         const int* mt_map, double* NU, double* BV, double* BU, double* PV, double* PW,
                                         double* PD, double* POWT, double* POWB, double* A00r, double* r0r) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: slot tests are scalar branches
   const int E2 = 2 * p - 1;
   const double ic2 = 1.0 / (cr * cr);
   for (int i = tid; i < (NS + 1) * M2 + (NS + 1) * M1 + Mm; i += blockDim.x) NU[i] = 0.0;
+  const int nslot0 = (ntile + 3) >> 2;  // slots of wave 0 (the most): tiles wave + 4 s
   double sw_acc = 0.0, su_acc = 0.0;
+  // bottom tasks: groups of waves (every task of the group in one slot when
+  // nsplit > 1, so the groups never write a moment word in the same pass)
+  const int nwt = max(1, (ntask1 + 63) >> 6);
+  const int nsplit = (blockDim.x == 256 && nwt <= 2) ? 4 / nwt : 1;
+  const int span = blockDim.x / nsplit, split = tid / span, ttask = tid - split * span;
   TaskRegs<kTaskSlots1> RB;
-  load_tasks(task1, ntask1, RB);
+  load_tasks(task1, ntask1, RB, ttask, span);
+  double bu0[4], bv0[4][NS + 1];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    bu0[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q <= NS; ++q) bv0[c][q] = 0.0;
+  }
+  // sums of the task in slot sl over the points split, split + nsplit, ... < nc
+  auto bottom_sums = [&](int sl, int nc, double (&bu)[4], double (&bv)[4][NS + 1]) {
+    const unsigned w0 = RB.w0[sl];
+    int e[NS];
+#pragma unroll
+    for (int v = 0; v < NS; ++v) e[v] = task_exp(w0, v);
+    const int d0 = task_exp(w0, 3);
+#pragma unroll 4
+    for (int pt = split; pt < nc; pt += nsplit) {
+      const double* pw = POWB + pt * (NS + 1) * (p + 1);
+      double pre = pw[e[0]];
+#pragma unroll
+      for (int v = 1; v < NS; ++v) pre *= pw[v * (p + 1) + e[v]];
+      const double z = pw[NS * (p + 1) + 1];
+      double mv = pre * pw[NS * (p + 1) + d0];
+      const double w = PW[pt];
+      double dd[NS + 1];
+#pragma unroll
+      for (int q = 0; q <= NS; ++q) dd[q] = PD[pt * (NS + 2) + q];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        bu[c] += w * mv;
+#pragma unroll
+        for (int q = 0; q <= NS; ++q) bv[c][q] += dd[q] * mv;
+        mv *= z;
+      }
+    }
+  };
+  auto bottom_flush = [&](int sl, const double (&bu)[4], const double (&bv)[4][NS + 1]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = task_idx(RB, sl, c);
+      if (k < 0) continue;
+      BU[k] += bu[c];
+      if (k < M1)
+#pragma unroll
+        for (int q = 0; q <= NS; ++q) BV[q * M1 + k] += bv[c][q];
+    }
+  };
   unsigned tex[kMomTileSlots];
   d4 acc[kMomTileSlots];
 #pragma unroll
@@ -847,10 +916,10 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         const double* Rn = EL + gel[c / cpe] * ELS;
         const double* st = state + (size_t)(int)Rn[El<NS>::E] * (NS + 2) * Q;
 #pragma unroll
-        for (int k = 0; k < NS + 2; ++k) g_st[k] = st[k * Q + q];
+        for (int k = 0; k < NS + 2; ++k) g_st[k] = gload(st + k * Q + q);
 #pragma unroll
-        for (int k = 0; k <= NS; ++k) g_lam[k] = lam_ref[(size_t)q * (NS + 1) + k];
-        g_w = w_ref[q];
+        for (int k = 0; k <= NS; ++k) g_lam[k] = gload(lam_ref + (size_t)q * (NS + 1) + k);
+        g_w = gload(w_ref + q);
       }
     }
   };
@@ -859,7 +928,7 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
     const int ei = cc / cpe, q0 = (cc % cpe) * PCH;
     const double* R = EL + gel[ei] * ELS;
     {
-      const int nc = min(PCH, Q - q0);
+      const int nc = min(PCH, Q - q0), nc4 = (nc + 3) & ~3;
       if (tid < nc) {
         const int pt = tid;
         const int lV = (int)R[El<NS>::LV];
@@ -885,16 +954,25 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
           PV[(PCH + pt) * (NS + 1) + 1 + d] = xh;
         }
         PW[pt] = w;
+      } else if (tid < nc4) {
+        // points past the chunk up to the next multiple of 4: weight 0 and zero
+        // coordinates, so that the top tiles read finite powers and add nothing
+        const int pt = tid;
+        for (int v = 0; v <= NS; ++v) PV[pt * (NS + 1) + v] = 0.0;
+        PW[pt] = 0.0;
       }
       __syncthreads();
-      for (int i = tid; i < nc * (NS + 1); i += blockDim.x) {
+      // powers of the top coordinates (those of th times the weight: the A
+      // operand of the top tiles is w L) for nc4 points, of the bottom ones for nc
+      for (int i = tid; i < nc4 * (NS + 1); i += blockDim.x) {
         const int pt = i / (NS + 1), v = i % (NS + 1);
-        double x = PV[pt * (NS + 1) + v], a = 1.0;
+        double x = PV[pt * (NS + 1) + v], a = v == 0 ? PW[pt] : 1.0;
         double* o = POWT + (pt * (NS + 1) + v) * E2;
         for (int ee = 0; ee < E2; ++ee) {
           o[ee] = a;
           a *= x;
         }
+        if (pt >= nc) continue;
         x = PV[(PCH + pt) * (NS + 1) + v];
         a = 1.0;
         o = POWB + (pt * (NS + 1) + v) * (p + 1);
@@ -909,35 +987,41 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
       fetch(cc + 1);
       // top moment tiles of this chunk.  The operand loads of all slots are issued
       // together: every index lies in this point's power row (a slot past the
-      // wave's tiles has exponents 0), and points past nc are masked by a select
-      // after the loads (their LDS words may hold anything)
-      const int nks = (nc + 3) >> 2;
-      for (int ks = 0; ks < nks; ++ks) {
-        const int pt = ks * 4 + (lane >> 4);
-        const bool ok = pt < nc;
-        const double* pw = POWT + pt * (NS + 1) * E2;
-        const double w = PW[pt];
-        double a[kMomTileSlots], b[kMomTileSlots];
+      // wave's tiles has exponents 0); the points past nc up to nc4 have weight 0
+      // Every wave runs the slot count of wave 0 (a compile-time count, so no
+      // branches in the loop): a slot past the wave's tiles accumulates finite
+      // values that are never folded.
+      const int nks = nc4 >> 2;
+      auto top_tiles = [&](auto nsl_c) {
+        constexpr int NSL = decltype(nsl_c)::value;
+        for (int ks = 0; ks < nks; ++ks) {
+          const int pt = ks * 4 + (lane >> 4);
+          const double* pw = POWT + pt * (NS + 1) * E2;
+          double a[NSL], b[NSL];
 #pragma unroll
-        for (int s = 0; s < kMomTileSlots; ++s) {
-          const unsigned ex = tex[s];
-          a[s] = w * pw[ex & 31u] * pw[E2 + ((ex >> 5) & 31u)];
-          b[s] = pw[2 * E2 + ((ex >> 10) & 31u)] * pw[3 * E2 + ((ex >> 15) & 31u)];
+          for (int s = 0; s < NSL; ++s) {
+            const unsigned ex = tex[s];
+            a[s] = pw[ex & 31u] * pw[E2 + ((ex >> 5) & 31u)];
+            b[s] = pw[2 * E2 + ((ex >> 10) & 31u)] * pw[3 * E2 + ((ex >> 15) & 31u)];
+          }
+#pragma unroll
+          for (int s = 0; s < NSL; ++s) acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc[s], 0, 0, 0);
         }
-#pragma unroll
-        for (int s = 0; s < kMomTileSlots; ++s)
-          if (wave + 4 * s < ntile)
-            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? a[s] : 0.0, ok ? b[s] : 0.0, acc[s], 0, 0, 0);
+      };
+      switch (nslot0) {
+        case 1: top_tiles(std::integral_constant<int, 1>{}); break;
+        case 2: top_tiles(std::integral_constant<int, 2>{}); break;
+        case 3: top_tiles(std::integral_constant<int, 3>{}); break;
+        case 4: top_tiles(std::integral_constant<int, 4>{}); break;
+        case 5: top_tiles(std::integral_constant<int, 5>{}); break;
+        default: top_tiles(std::integral_constant<int, kMomTileSlots>{}); break;
       }
-      // bottom moments (monomials of degree <= p), VALU tasks
+      // bottom moments (monomials of degree <= p), VALU tasks: slot 0 keeps its
+      // sums over all chunks, later slots (only with nsplit = 1) add theirs now
+      if (ttask < ntask1) bottom_sums(0, nc, bu0, bv0);
 #pragma unroll
-      for (int sl = 0; sl < kTaskSlots1; ++sl) {
-        if (tid + sl * (int)blockDim.x >= ntask1) break;
-        const unsigned w0 = RB.w0[sl];
-        int e[NS];
-#pragma unroll
-        for (int v = 0; v < NS; ++v) e[v] = task_exp(w0, v);
-        const int d0 = task_exp(w0, 3);
+      for (int sl = 1; sl < kTaskSlots1; ++sl) {
+        if (ttask + sl * span >= ntask1) break;
         double bu[4], bv[4][NS + 1];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -945,35 +1029,8 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
 #pragma unroll
           for (int q = 0; q <= NS; ++q) bv[c][q] = 0.0;
         }
-#pragma unroll 4
-        for (int pt = 0; pt < nc; ++pt) {
-          const double* pw = POWB + pt * (NS + 1) * (p + 1);
-          double pre = pw[e[0]];
-#pragma unroll
-          for (int v = 1; v < NS; ++v) pre *= pw[v * (p + 1) + e[v]];
-          const double z = pw[NS * (p + 1) + 1];
-          double mv = pre * pw[NS * (p + 1) + d0];
-          const double w = PW[pt];
-          double dd[NS + 1];
-#pragma unroll
-          for (int q = 0; q <= NS; ++q) dd[q] = PD[pt * (NS + 2) + q];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            bu[c] += w * mv;
-#pragma unroll
-            for (int q = 0; q <= NS; ++q) bv[c][q] += dd[q] * mv;
-            mv *= z;
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int k = task_idx(RB, sl, c);
-          if (k < 0) continue;
-          BU[k] += bu[c];
-          if (k < M1)
-#pragma unroll
-            for (int q = 0; q <= NS; ++q) BV[q * M1 + k] += bv[c][q];
-        }
+        bottom_sums(sl, nc, bu, bv);
+        bottom_flush(sl, bu, bv);
       }
       if (tid == blockDim.x - 1)
         for (int pt = 0; pt < nc; ++pt) {
@@ -1002,12 +1059,17 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
               for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += g[d] * c;
             }
           }
-          acc[s] = d4{0.0, 0.0, 0.0, 0.0};
         }
+        acc[s] = d4{0.0, 0.0, 0.0, 0.0};
       }
     }
   }
   __syncthreads();
+  // slot 0's sums of the groups, group by group
+  for (int s = 0; s < nsplit; ++s) {
+    if (split == s && ttask < ntask1) bottom_flush(0, bu0, bv0);
+    __syncthreads();
+  }
   if (tid == blockDim.x - 1) {
     *A00r += sw_acc;
     *r0r += su_acc;
@@ -1057,14 +1119,17 @@ __device__ inline void eval_runs(const Tab& T, const int* runs, const double* va
 // with CM_c the dense coefficients (rows a < nA16, row stride ldb).  Y is a
 // 16x16x4 MFMA chain per tile of 16 entries a (A: R_b at point l%16, entry b =
 // 4 ks + l/16; B: CM_c[a = 16 I + l%16][b]); tile I needs nks[I] steps (the
-// entries b of degree <= p minus the tile's smallest degree).  Each lane then
+// entries b of degree <= p minus the tile's smallest degree), and nkv[I] for
+// the first NV fields (v and sigma: degree <= p - 1; the steps past nkv[I]
+// would only add exact zeros).  Each lane then
 // weights its four results (points l/16 + 4r, entry 16 I + l%16) by L_a and
 // the 16 lanes of a row are summed: every lane of row l/16 ends with val[c][r]
 // of point l/16 + 4r.  PWW: powers of the wave's 16 points, PWW[(pt*4 + v)*P1
 // + e] = var_v^e (v = 0: th).
-template <int NC>
+template <int NC, int NV>
 __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl, int nat, const int* nks,
-                                   const int* EX, const double* PWW, int P1, double (&val)[NC][4]) {
+                                   const int* nkv, const int* EX, const double* PWW, int P1,
+                                   double (&val)[NC][4]) {
   constexpr int KMAX = kEvalMaxSteps;
   const int lane = threadIdx.x & 63;
   const int pi = lane & 15, kq = lane >> 4;
@@ -1074,7 +1139,7 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
     for (int r = 0; r < 4; ++r) val[c][r] = 0.0;
   // the A operands R_b(point pi), b = 4 ks + kq, once for every field and tile
   // (tile 0 needs the most steps)
-  const int nk0 = nks[0];
+  const int nk0 = NV < NC ? nks[0] : nkv[0];
   double rv[KMAX];
   {
     const double* pw = PWW + pi * 4 * P1;
@@ -1097,7 +1162,8 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
       const double* pw = PWW + (kq + 4 * r) * 4 * P1;
       La[r] = a < nl ? pw[ea & 255] * pw[P1 + (ea >> 8)] : 0.0;
     }
-    const int nk = nks[I];
+    const int nkvI = nkv[I];
+    const int nk = NV < NC ? nks[I] : nkvI;
     d4 acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
@@ -1106,11 +1172,14 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
     for (int ks = 0; ks < KMAX; ++ks) {
       if (ks < nk) {
         const int b = ks * 4 + kq;
+        const bool sv = ks < nkvI;  // the first NV fields (degree <= p - 1) need fewer steps
         double bv[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) bv[c] = b < nl ? CMd[((long long)c * nA16 + a) * ldb + b] : 0.0;
+        for (int c = 0; c < NC; ++c)
+          bv[c] = (b < nl && (c >= NV || sv)) ? CMd[((long long)c * nA16 + a) * ldb + b] : 0.0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[ks], bv[c], acc[c], 0, 0, 0);
+        for (int c = 0; c < NC; ++c)
+          if (c >= NV || sv) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[ks], bv[c], acc[c], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -1146,7 +1215,7 @@ __device__ inline void build_cm_dense(const Tab& T, const TableDesc& Dp, const d
 }
 
 template <int NS, int TPW, bool MIXED, bool MOM>
-__device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, double* lds) {
+__device__ __attribute__((always_inline)) void solve_tent(const KParams& P, const LdsPlan& L, const int tent, double* lds) {
   __shared__ int s_m, s_piv, s_err, s_goff[kMaxGroups + 1], s_conv;
   __shared__ double s_red[2 * kBlock / 64];
   __shared__ int s_gel[kMaxPatch];
@@ -2432,7 +2501,7 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
             }
             wave_sync();
             double val[NS + 1][4];
-            eval16_mfma<NS + 1>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, EXs, pwv, P1, val);
+            eval16_mfma<NS + 1, NS + 1>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, Dp.ev_nkv, EXs, pwv, P1, val);
             if ((lane & 15) == 0) {
 #pragma unroll
               for (int rr = 0; rr < 4; ++rr) {
@@ -2553,7 +2622,7 @@ __device__ void solve_tent(const KParams& P, const LdsPlan& L, const int tent, d
           }
           wave_sync();
           double val[NS + 2][4];
-          eval16_mfma<NS + 2>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, EXs, pwv, P1, val);
+          eval16_mfma<NS + 2, NS + 1>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, Dp.ev_nkv, EXs, pwv, P1, val);
           if ((lane & 15) == 0) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {

@@ -362,6 +362,9 @@ Table build_table(int n, int p) {
         const int dmin = lst[16 * I][0] + lst[16 * I][1];
         const int need = (p - dmin + 1) * (p - dmin + 2) / 2;  // entries of degree <= p - dmin
         T.ev_nks[I] = (need + 3) / 4;
+        // v and sigma have degree <= p - 1: entries of degree <= p - 1 - dmin
+        const int bv = p - 1 - dmin;
+        T.ev_nkv[I] = bv < 0 ? 0 : ((bv + 1) * (bv + 2) / 2 + 3) / 4;
       }
       for (int k = 0; k < T.M; ++k) {
         const int* e = &T.expo[(size_t)k * (n + 1)];

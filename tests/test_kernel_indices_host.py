@@ -58,6 +58,32 @@ def _check_tasks(task, ntask, slots, n_idx, max_exp, n):
     assert (seen == 1).all()
 
 
+def _check_bottom_groups(ntask1, Q, pch):
+    """Bottom moments of the 3+1D moment loop: with at most 64 (128) tasks they
+    are repeated over 4 (2) groups of waves; thread tid is group tid // span,
+    task tid % span (+ slot * span) and takes the points group, group +
+    nsplit, ... of a chunk.  Every (task, point) pair is summed exactly once,
+    and with more than one group every task sits in slot 0 (the slot whose sums
+    the groups add one after another after the last chunk)."""
+    nwt = max(1, (ntask1 + 63) // 64)
+    nsplit = 4 // nwt if nwt <= 2 else 1
+    span = K_BLOCK // nsplit
+    if nsplit > 1:
+        assert ntask1 <= span
+    for nc in {pch, Q % pch or pch, 1}:
+        seen = np.zeros((ntask1, nc), np.int64)
+        for tid in range(K_BLOCK):
+            g, tt = tid // span, tid % span
+            for sl in range(K_TASK_SLOTS1):
+                t = tt + sl * span
+                if t >= ntask1:
+                    break
+                assert sl == 0 or nsplit == 1
+                for pt in range(g, nc, nsplit):
+                    seen[t, pt] += 1
+        assert (seen == 1).all()
+
+
 def _degree_blocks(D):
     lst = [(a, d - a) for d in range(D + 1) for a in range(d, -1, -1)]
     nb = (len(lst) + 15) // 16
@@ -84,6 +110,7 @@ def test_moment_phase_indices_stay_in_bounds_3d(p_max):
         # VALU moment tasks (moment_points, face moments, write-back runs)
         _check_tasks(task2, d["ntask2"], K_TASK_SLOTS, M2, max(2 * p - 2, 0), n)
         _check_tasks(task1, d["ntask1"], K_TASK_SLOTS1, M, p, n)
+        _check_bottom_groups(d["ntask1"], Q, PCH)
         # LDS regions: powers of the top (E2) and bottom (p+1) points, moments
         pow_region = d["off_W1"] - d["off_pow"]
         assert PCH * (n + 1) * E2 + PCH * (n + 1) * (p + 1) <= pow_region
@@ -165,10 +192,11 @@ def test_matrix_core_evaluation_indices_3d(p_max, gram_mode):
     f.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     f.restype = ctypes.c_int
     for p in range(1, p_max + 1):
-        info = np.zeros(14, np.int32)
+        info = np.zeros(22, np.int32)
         assert f(ctx._h, p, info.ctypes.data, None, None) == 0
         nl, nat, nks, M, w1 = int(info[0]), int(info[1]), info[2:10], int(info[10]), int(info[11])
         mpch, moff = int(info[12]), int(info[13])
+        nkv = info[14:22]
         if moff >= 0:
             # the larger moment chunk of this degree sits behind its moments in W1:
             # points (2 (n+1) + 1 + (n+2) doubles each) and powers (E2 + p + 1 per
@@ -185,10 +213,15 @@ def test_matrix_core_evaluation_indices_3d(p_max, gram_mode):
         assert lst == [(a, d - a) for d in range(p + 1) for a in range(d, -1, -1)]
         pairs = [(int(x) & 0xFFFF, int(x) >> 16) for x in ab]
         assert len(set(pairs)) == M
-        for a, b in pairs:
+        for k, (a, b) in enumerate(pairs):
             assert a < nl and b < nl and sum(lst[a]) + sum(lst[b]) <= p
-            # the pair is reached by the k-steps of a's tile
+            # the pair is reached by the k-steps of a's tile; the monomials of
+            # degree <= p - 1 (those of v and sigma: the first C(p+3, 4)) by the
+            # shorter step count of the tile
             assert b < 4 * nks[a // 16]
+            if k < comb(p - 1 + 4, 4):
+                assert b < 4 * nkv[a // 16]
+        assert all(nkv[I] <= nks[I] for I in range(nat))
         ldb = nl | 1
         nA16 = 16 * nat
         dense = 5 * nA16 * ldb
