@@ -853,25 +853,34 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
 #pragma unroll
     for (int q = 0; q <= NS; ++q) bv0[c][q] = 0.0;
   }
-  // sums of the task in slot sl over the points split, split + nsplit, ... < nc
+  // sums of the task in slot sl over the points split, split + nsplit, ... < nc;
+  // the LDS words of the next point are loaded before the current point's
+  // products (the last point loads itself again)
   auto bottom_sums = [&](int sl, int nc, double (&bu)[4], double (&bv)[4][NS + 1]) {
     const unsigned w0 = RB.w0[sl];
     int e[NS];
 #pragma unroll
     for (int v = 0; v < NS; ++v) e[v] = task_exp(w0, v);
     const int d0 = task_exp(w0, 3);
-#pragma unroll 4
-    for (int pt = split; pt < nc; pt += nsplit) {
+    if (split >= nc) return;
+    double f[NS + 1], z, w, dd[NS + 1];
+    auto load = [&](int pt, double (&f_)[NS + 1], double& z_, double& w_, double (&dd_)[NS + 1]) {
       const double* pw = POWB + pt * (NS + 1) * (p + 1);
-      double pre = pw[e[0]];
 #pragma unroll
-      for (int v = 1; v < NS; ++v) pre *= pw[v * (p + 1) + e[v]];
-      const double z = pw[NS * (p + 1) + 1];
-      double mv = pre * pw[NS * (p + 1) + d0];
-      const double w = PW[pt];
-      double dd[NS + 1];
+      for (int v = 0; v < NS; ++v) f_[v] = pw[v * (p + 1) + e[v]];
+      f_[NS] = pw[NS * (p + 1) + d0];
+      z_ = pw[NS * (p + 1) + 1];
+      w_ = PW[pt];
 #pragma unroll
-      for (int q = 0; q <= NS; ++q) dd[q] = PD[pt * (NS + 2) + q];
+      for (int q = 0; q <= NS; ++q) dd_[q] = PD[pt * (NS + 2) + q];
+    };
+    load(split, f, z, w, dd);
+    for (int pt = split; pt < nc; pt += nsplit) {
+      double fn[NS + 1], zn, wn, ddn[NS + 1];
+      load(min(pt + nsplit, nc - 1), fn, zn, wn, ddn);
+      double mv = f[0];
+#pragma unroll
+      for (int v = 1; v <= NS; ++v) mv *= f[v];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         bu[c] += w * mv;
@@ -879,6 +888,12 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         for (int q = 0; q <= NS; ++q) bv[c][q] += dd[q] * mv;
         mv *= z;
       }
+#pragma unroll
+      for (int v = 0; v <= NS; ++v) f[v] = fn[v];
+      z = zn;
+      w = wn;
+#pragma unroll
+      for (int q = 0; q <= NS; ++q) dd[q] = ddn[q];
     }
   };
   auto bottom_flush = [&](int sl, const double (&bu)[4], const double (&bv)[4][NS + 1]) {
@@ -992,20 +1007,33 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
       // branches in the loop): a slot past the wave's tiles accumulates finite
       // values that are never folded.
       const int nks = nc4 >> 2;
+      // The power words of step ks + 1 are loaded before the products of step ks
+      // (the last step loads itself again).
       auto top_tiles = [&](auto nsl_c) {
         constexpr int NSL = decltype(nsl_c)::value;
-        for (int ks = 0; ks < nks; ++ks) {
-          const int pt = ks * 4 + (lane >> 4);
-          const double* pw = POWT + pt * (NS + 1) * E2;
-          double a[NSL], b[NSL];
+        double f[NSL][4];
+        auto load = [&](int ks, double (&f_)[NSL][4]) {
+          const double* pw = POWT + (ks * 4 + (lane >> 4)) * (NS + 1) * E2;
 #pragma unroll
           for (int s = 0; s < NSL; ++s) {
             const unsigned ex = tex[s];
-            a[s] = pw[ex & 31u] * pw[E2 + ((ex >> 5) & 31u)];
-            b[s] = pw[2 * E2 + ((ex >> 10) & 31u)] * pw[3 * E2 + ((ex >> 15) & 31u)];
+            f_[s][0] = pw[ex & 31u];
+            f_[s][1] = pw[E2 + ((ex >> 5) & 31u)];
+            f_[s][2] = pw[2 * E2 + ((ex >> 10) & 31u)];
+            f_[s][3] = pw[3 * E2 + ((ex >> 15) & 31u)];
           }
+        };
+        load(0, f);
+        for (int ks = 0; ks < nks; ++ks) {
+          double fn[NSL][4];
+          load(min(ks + 1, nks - 1), fn);
 #pragma unroll
-          for (int s = 0; s < NSL; ++s) acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc[s], 0, 0, 0);
+          for (int s = 0; s < NSL; ++s)
+            acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[s][0] * f[s][1], f[s][2] * f[s][3], acc[s], 0, 0, 0);
+#pragma unroll
+          for (int s = 0; s < NSL; ++s)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) f[s][j] = fn[s][j];
         }
       };
       switch (nslot0) {
