@@ -66,6 +66,30 @@ __device__ inline double gload(const double* p) {
   return *(const __attribute__((address_space(1))) double*)p;
 }
 
+// Sums of a and b over the workgroup (lanes by butterflies, then the waves in
+// order; deterministic): every thread returns the totals.  scratch: 2 doubles per
+// wave of LDS, free for the call; the call starts and ends with a barrier.
+__device__ inline void block_sum2(double& a, double& b, double* scratch) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    scratch[2 * wave] = a;
+    scratch[2 * wave + 1] = b;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  for (int w = 0; w < (int)blockDim.x / 64; ++w) {
+    a += scratch[2 * w];
+    b += scratch[2 * w + 1];
+  }
+  __syncthreads();
+}
+
 // ordering of LDS accesses inside one wave (no workgroup barrier needed)
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -685,6 +709,8 @@ __device__ inline void moment_points(const double* lam_ref, const double* w_ref,
         PG[pt * NS + d] = w * R[El<NS>::GNEW + d];
       }
       PW[pt] = w;
+      sw_acc += w;
+      su_acc += PD[pt * (NS + 2) + NS + 1];
     }
     __syncthreads();
     for (int i = tid; i < nc * (NS + 1); i += blockDim.x) {
@@ -796,14 +822,11 @@ __device__ inline void moment_points(const double* lam_ref, const double* w_ref,
           for (int q = 0; q <= NS; ++q) BV[q * M1 + k] += bv[c][q];
       }
     }
-    if (tid == blockDim.x - 1)
-      for (int pt = 0; pt < nc; ++pt) {
-        sw_acc += PW[pt];
-        su_acc += PD[pt * (NS + 2) + NS + 1];
-      }
     __syncthreads();
   }
-  if (tid == blockDim.x - 1) {
+  // the recovery row's weight and U sums: each set-up thread's, then the block's
+  block_sum2(sw_acc, su_acc, PW);
+  if (tid == 0) {
     *A00r += sw_acc;
     *r0r += su_acc;
   }
@@ -896,6 +919,30 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
       for (int q = 0; q <= NS; ++q) dd[q] = ddn[q];
     }
   };
+  // slot 0: exponents of the task's prefix and run start, and the sums of one point
+  int e0x[NS], d0x;
+#pragma unroll
+  for (int v = 0; v < NS; ++v) e0x[v] = task_exp(RB.w0[0], v);
+  d0x = task_exp(RB.w0[0], 3);
+  auto bottom_point0 = [&](int pt) {
+    const double* pw = POWB + pt * (NS + 1) * (p + 1);
+    double mv = pw[e0x[0]];
+#pragma unroll
+    for (int v = 1; v < NS; ++v) mv *= pw[v * (p + 1) + e0x[v]];
+    mv *= pw[NS * (p + 1) + d0x];
+    const double z = pw[NS * (p + 1) + 1];
+    const double w = PW[pt];
+    double dd[NS + 1];
+#pragma unroll
+    for (int q = 0; q <= NS; ++q) dd[q] = PD[pt * (NS + 2) + q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      bu0[c] += w * mv;
+#pragma unroll
+      for (int q = 0; q <= NS; ++q) bv0[c][q] += dd[q] * mv;
+      mv *= z;
+    }
+  };
   auto bottom_flush = [&](int sl, const double (&bu)[4], const double (&bv)[4][NS + 1]) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -969,6 +1016,8 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
           PV[(PCH + pt) * (NS + 1) + 1 + d] = xh;
         }
         PW[pt] = w;
+        sw_acc += w;
+        su_acc += w * g_st[NS + 1];
       } else if (tid < nc4) {
         // points past the chunk up to the next multiple of 4: weight 0 and zero
         // coordinates, so that the top tiles read finite powers and add nothing
@@ -1008,7 +1057,11 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
       // values that are never folded.
       const int nks = nc4 >> 2;
       // The power words of step ks + 1 are loaded before the products of step ks
-      // (the last step loads itself again).
+      // (the last step loads itself again).  The bottom moments of slot 0 for the
+      // step's points of this wave group (pt = 4 ks + split + j, j a multiple of
+      // nsplit) run on the VALU between the step's matrix-core instructions,
+      // which execute meanwhile; every group takes its points in ascending order.
+      const bool bot0 = ttask < ntask1;
       auto top_tiles = [&](auto nsl_c) {
         constexpr int NSL = decltype(nsl_c)::value;
         double f[NSL][4];
@@ -1030,6 +1083,13 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
 #pragma unroll
           for (int s = 0; s < NSL; ++s)
             acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[s][0] * f[s][1], f[s][2] * f[s][3], acc[s], 0, 0, 0);
+          if (bot0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int pt = 4 * ks + split + j;
+              if ((j & (nsplit - 1)) == 0 && pt < nc) bottom_point0(pt);
+            }
+          }
 #pragma unroll
           for (int s = 0; s < NSL; ++s)
 #pragma unroll
@@ -1044,9 +1104,9 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         case 5: top_tiles(std::integral_constant<int, 5>{}); break;
         default: top_tiles(std::integral_constant<int, kMomTileSlots>{}); break;
       }
-      // bottom moments (monomials of degree <= p), VALU tasks: slot 0 keeps its
-      // sums over all chunks, later slots (only with nsplit = 1) add theirs now
-      if (ttask < ntask1) bottom_sums(0, nc, bu0, bv0);
+      // bottom moments (monomials of degree <= p), VALU tasks: slot 0 (inside the
+      // top-tile steps above) keeps its sums over all chunks, later slots (only
+      // with nsplit = 1) add theirs now
 #pragma unroll
       for (int sl = 1; sl < kTaskSlots1; ++sl) {
         if (ttask + sl * span >= ntask1) break;
@@ -1060,11 +1120,6 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
         bottom_sums(sl, nc, bu, bv);
         bottom_flush(sl, bu, bv);
       }
-      if (tid == blockDim.x - 1)
-        for (int pt = 0; pt < nc; ++pt) {
-          sw_acc += PW[pt];
-          su_acc += PD[pt * (NS + 2) + NS + 1];
-        }
       __syncthreads();
     }
     // after the element's last chunk: fold its tiles (each moment index belongs
@@ -1098,7 +1153,9 @@ __device__ inline void moment_points_mt(const double* lam_ref, const double* w_r
     if (split == s && ttask < ntask1) bottom_flush(0, bu0, bv0);
     __syncthreads();
   }
-  if (tid == blockDim.x - 1) {
+  // the recovery row's weight and U sums: each set-up thread's, then the block's
+  block_sum2(sw_acc, su_acc, PW);
+  if (tid == 0) {
     *A00r += sw_acc;
     *r0r += su_acc;
   }
@@ -1597,6 +1654,7 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
     float* PSI32 = reinterpret_cast<float*>(PSI);
     double rhs_acc = 0.0, a0_acc = 0.0;    // column j = tid
     double rhs_acc2 = 0.0, a0_acc2 = 0.0;  // column j = tid + blockDim.x
+    double sw_acc = 0.0, su_acc = 0.0;     // recovery row: this thread's set-up points
     for (int f0 = 0; f0 < npts; f0 += PCH) {
       const int nc = min(PCH, npts - f0);
       // point set-up
@@ -1650,6 +1708,8 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
         PW[pt] = w;
         PS[pt] = sD;
         for (int k = 0; k < NS + 2; ++k) PD[pt * (NS + 2) + k] = dd[k];
+        sw_acc += w;
+        su_acc += dd[NS + 1];
       }
       __syncthreads();
       // powers and monomials of the top and bottom points
@@ -1741,15 +1801,6 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
           a0_acc2 += s2;
         }
       }
-      if (tid == blockDim.x - 1 && pass == 0) {
-        double sw = 0.0, su = 0.0;
-        for (int pt = 0; pt < nc; ++pt) {
-          sw += PW[pt];
-          su += PD[pt * (NS + 2) + NS + 1];
-        }
-        A00[r] += sw;
-        r0[r] += su;
-      }
       __syncthreads();
     }
     // Gram tiles of block (r, r): element e of lane l is row l/16 + 4e, column l%16
@@ -1773,6 +1824,14 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
             if (I != J) A[(long long)(r * NW + j) * lda + r * NW + i] += val;
           }
         }
+      }
+    }
+    if (pass == 0) {
+      // the recovery row's weight and U sums: each set-up thread's, then the block's
+      block_sum2(sw_acc, su_acc, s_red);
+      if (tid == 0) {
+        A00[r] += sw_acc;
+        r0[r] += su_acc;
       }
     }
     if (pass == 0 && tid < NW) {
