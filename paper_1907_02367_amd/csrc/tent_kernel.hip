@@ -513,35 +513,37 @@ __device__ inline bool panel_lu_solve(double* A, long long lda, int S, int nb, d
 // Solves one tent; called by every thread of the workgroup.  All early returns
 // are taken by the whole workgroup (their conditions are workgroup-uniform).
 
-// Gram block (r, r) of a tent from the moments NU (moment mode), one test
-// function i at a time:  Z[b][l] = sum over the terms (a, k, al) of function i
-// of al H_ab(k, l), then A_ij += sum over the terms (b, l, be) of function j of
-// be Z[b][l].  Top Gram (dirichlet = false): H_00 = H_dd = nu, H_0d = H_d0 =
-// -c nu_d (lower triangle computed, mirrored).  Dirichlet faces (dirichlet =
-// true): H_00 = alpha c^2 nu, H_0d = c nu_d (row v, column sigma_d), all j.
-template <int NS>
-__device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, const double* fo_coef,
-                                               const int* K2, int M1, int M2, int NW, const double* NU, double* Z,
-                                               double cr, double alpha, bool dirichlet, double* A, long long lda,
-                                               int row0) {
+// Gram block (r, r) of a tent from the moments NU (moment mode), NZ test
+// functions i = i0 .. i0+NZ-1 at a time:  Z_i[b][l] = sum over the terms
+// (a, k, al) of function i of al H_ab(k, l) (one thread per (i, l)), then
+// A_ij += sum over the terms (b, l, be) of function j of be Z_i[b][l] (one
+// thread per j, the table terms of j loaded once for the NZ rows).  Top Gram
+// (dirichlet = false): H_00 = H_dd = nu, H_0d = H_d0 = -c nu_d (lower triangle
+// computed, mirrored).  Dirichlet faces (dirichlet = true): H_00 = alpha c^2 nu,
+// H_0d = c nu_d (row v, column sigma_d), all j.  Every sum keeps the term order
+// of the table, so the result does not depend on NZ.
+template <int NS, int NZ>
+__device__ inline void moment_gram_pass(const int* fo_ptr, const int* fo_idx, const double* fo_coef,
+                                        const int* K2, int M1, int M2, int NW, const double* NU, double* Z,
+                                        double cr, double alpha, bool dirichlet, double* A, long long lda,
+                                        int row0) {
   const int tid = threadIdx.x;
   const double ca = alpha * cr * cr;
-  for (int i = 0; i < NW; ++i) {
-    // Z[b][l] of test function i: each thread keeps the columns l = tid + s*blockDim.x
-    // (two per pass) in registers over all table terms of i, in term order
-    for (int l0 = 0; l0 < M1; l0 += 2 * (int)blockDim.x) {
-      double z[2][NS + 1];
+  for (int i0 = 0; i0 < NW; i0 += NZ) {
+    const int nzi = min(NZ, NW - i0);
+    // Z of the functions i0 + q: item q M1 + l, its sums in registers over all
+    // table terms of the function (in term order); terms in groups of four with
+    // their product-index loads (global) issued together, a missing term entering
+    // with coefficient 0 at index 0
+    for (int it = tid; it < nzi * M1; it += blockDim.x) {
+      const int q = it / M1, l = it - q * M1, i = i0 + q;
+      double z[NS + 1];
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int c = 0; c <= NS; ++c) z[s][c] = 0.0;
+      for (int c = 0; c <= NS; ++c) z[c] = 0.0;
       const int amax = dirichlet ? 0 : NS;
       for (int a = 0; a <= amax; ++a) {
         const int row = i * (NS + 1) + a;
         const int e1 = fo_ptr[row + 1];
-        // terms in groups of four: their product-index loads (global) are issued
-        // together; a missing term enters with coefficient 0 at index 0 (adding
-        // zero leaves every sum unchanged, the order of the terms is kept)
         for (int e = fo_ptr[row]; e < e1; e += 4) {
           int kk[4];
           double al[4];
@@ -550,57 +552,45 @@ __device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, c
             kk[u] = e + u < e1 ? fo_idx[e + u] : 0;
             al[u] = e + u < e1 ? fo_coef[e + u] : 0.0;
           }
-          int b2[4][2];
+          int b2[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 4; ++u) b2[u] = K2[kk[u] * M1 + l];
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-              const int l = l0 + tid + s * (int)blockDim.x;
-              b2[u][s] = l < M1 ? K2[kk[u] * M1 + l] : 0;
+          for (int u = 0; u < 4; ++u) {
+            const int b = b2[u];
+            if (dirichlet) {
+              z[0] += ca * al[u] * NU[b];
+#pragma unroll
+              for (int d = 0; d < NS; ++d) z[1 + d] += cr * al[u] * NU[(1 + d) * M2 + b];
+            } else if (a == 0) {
+              z[0] += al[u] * NU[b];
+#pragma unroll
+              for (int d = 0; d < NS; ++d) z[1 + d] -= cr * al[u] * NU[(1 + d) * M2 + b];
+            } else {
+#pragma unroll
+              for (int c = 1; c <= NS; ++c)
+                if (c == a) z[c] += al[u] * NU[b];
+              z[0] -= cr * al[u] * NU[a * M2 + b];
             }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-              const int l = l0 + tid + s * (int)blockDim.x;
-              if (l < M1) {
-                const int b = b2[u][s];
-                if (dirichlet) {
-                  z[s][0] += ca * al[u] * NU[b];
-#pragma unroll
-                  for (int d = 0; d < NS; ++d) z[s][1 + d] += cr * al[u] * NU[(1 + d) * M2 + b];
-                } else if (a == 0) {
-                  z[s][0] += al[u] * NU[b];
-#pragma unroll
-                  for (int d = 0; d < NS; ++d) z[s][1 + d] -= cr * al[u] * NU[(1 + d) * M2 + b];
-                } else {
-#pragma unroll
-                  for (int c = 1; c <= NS; ++c)
-                    if (c == a) z[s][c] += al[u] * NU[b];
-                  z[s][0] -= cr * al[u] * NU[a * M2 + b];
-                }
-              }
-            }
+          }
         }
       }
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int l = l0 + tid + s * (int)blockDim.x;
-        if (l < M1)
-#pragma unroll
-          for (int c = 0; c <= NS; ++c) Z[c * M1 + l] = z[s][c];
-      }
+      for (int c = 0; c <= NS; ++c) Z[(q * (NS + 1) + c) * M1 + l] = z[c];
     }
     __syncthreads();
-    const int jmax = dirichlet ? NW - 1 : i;
+    const int jmax = dirichlet ? NW - 1 : i0 + nzi - 1;
     for (int j = tid; j <= jmax; j += blockDim.x) {
       // the terms of function j (components b = 0..NS, consecutive in the table)
-      // eight at a time: their table loads are issued together; the sum keeps
-      // the term order
+      // eight at a time: their table loads are issued together; each row's sum
+      // keeps the term order (rows q >= nzi read words of no function and are
+      // not stored)
       int bnd[NS + 2];
 #pragma unroll
       for (int b = 0; b <= NS + 1; ++b) bnd[b] = fo_ptr[j * (NS + 1) + b];
-      double acc = 0.0;
+      double acc[NZ];
+#pragma unroll
+      for (int q = 0; q < NZ; ++q) acc[q] = 0.0;
       for (int e = bnd[0]; e < bnd[NS + 1]; e += 8) {
         int ix[8];
         double cf[8];
@@ -614,14 +604,38 @@ __device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, c
           int b = 0;
 #pragma unroll
           for (int c = 1; c <= NS; ++c) b += e + u >= bnd[c] ? 1 : 0;
-          if (e + u < bnd[NS + 1]) acc += cf[u] * Z[b * M1 + ix[u]];
+          if (e + u < bnd[NS + 1])
+#pragma unroll
+            for (int q = 0; q < NZ; ++q) acc[q] += cf[u] * Z[(q * (NS + 1) + b) * M1 + ix[u]];
         }
       }
-      A[(long long)(row0 + i) * lda + row0 + j] += acc;
-      if (!dirichlet && j != i) A[(long long)(row0 + j) * lda + row0 + i] += acc;
+#pragma unroll
+      for (int q = 0; q < NZ; ++q) {
+        const int i = i0 + q;
+        if (q < nzi && (dirichlet || j <= i)) {
+          A[(long long)(row0 + i) * lda + row0 + j] += acc[q];
+          if (!dirichlet && j != i) A[(long long)(row0 + j) * lda + row0 + i] += acc[q];
+        }
+      }
     }
     __syncthreads();
   }
+}
+
+// The Gram block with as many test functions per pass (1, 2 or 4) as the Z
+// rows fit in zcap doubles at Z.
+template <int NS>
+__device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, const double* fo_coef,
+                                         const int* K2, int M1, int M2, int NW, const double* NU, double* Z,
+                                         long long zcap, double cr, double alpha, bool dirichlet, double* A,
+                                         long long lda, int row0) {
+  const long long per = (long long)(NS + 1) * M1;
+  if (zcap >= 4 * per)
+    moment_gram_pass<NS, 4>(fo_ptr, fo_idx, fo_coef, K2, M1, M2, NW, NU, Z, cr, alpha, dirichlet, A, lda, row0);
+  else if (zcap >= 2 * per)
+    moment_gram_pass<NS, 2>(fo_ptr, fo_idx, fo_coef, K2, M1, M2, NW, NU, Z, cr, alpha, dirichlet, A, lda, row0);
+  else
+    moment_gram_pass<NS, 1>(fo_ptr, fo_idx, fo_coef, K2, M1, M2, NW, NU, Z, cr, alpha, dirichlet, A, lda, row0);
 }
 
 
@@ -1252,19 +1266,30 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
     d4 acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
-    // the fields' chains interleaved (independent accumulators)
+    // the fields' chains interleaved (independent accumulators); the B operands
+    // of step ks + 1 are loaded before the products of step ks
+    auto load_b = [&](int ks, double (&bv)[NC]) {
+      const int b = ks * 4 + kq;
+      const bool sv = ks < nkvI;  // the first NV fields (degree <= p - 1) need fewer steps
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        bv[c] = (b < nl && (c >= NV || sv)) ? CMd[((long long)c * nA16 + a) * ldb + b] : 0.0;
+    };
+    double bcur[NC];
+    load_b(0, bcur);
 #pragma unroll
     for (int ks = 0; ks < KMAX; ++ks) {
       if (ks < nk) {
-        const int b = ks * 4 + kq;
-        const bool sv = ks < nkvI;  // the first NV fields (degree <= p - 1) need fewer steps
-        double bv[NC];
+        double bnx[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) bnx[c] = 0.0;
+        if (ks + 1 < nk) load_b(ks + 1, bnx);
+        const bool sv = ks < nkvI;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-          bv[c] = (b < nl && (c >= NV || sv)) ? CMd[((long long)c * nA16 + a) * ldb + b] : 0.0;
+          if (c >= NV || sv) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[ks], bcur[c], acc[c], 0, 0, 0);
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (c >= NV || sv) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[ks], bv[c], acc[c], 0, 0, 0);
+        for (int c = 0; c < NC; ++c) bcur[c] = bnx[c];
       }
     }
 #pragma unroll
@@ -1621,7 +1646,9 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
       }
       __syncthreads();
       // Gram block (r, r) from the moments (Z reuses the bottom moments' space)
-      moment_gram_block<NS>(T.fo_ptr, T.fo_idx, T.fo_coef, T.K2, M1, M2, NW, NU, BV, cr, 0.0, false, A, lda, r * NW);
+      moment_gram_block<NS>(T.fo_ptr, T.fo_idx, T.fo_coef, T.K2, M1, M2, NW, NU, BV,
+                            (long long)(L.off_fg - L.off_W1) - (long long)(NS + 1) * M2, cr, 0.0, false, A, lda,
+                            r * NW);
     }
   } else {
   // ---- 2. top Gram (matrix cores), bottom right-hand side, U recovery rows --------
@@ -2116,7 +2143,8 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
           AT[(long long)(r * NW + i) * lda + S] += b;
         }
         __syncthreads();
-        moment_gram_block<NS>(T.fo_ptr, T.fo_idx, T.fo_coef, T.K2, M1, M2, NW, NU, BV, cr, P.alpha, true, AT, lda,
+        moment_gram_block<NS>(T.fo_ptr, T.fo_idx, T.fo_coef, T.K2, M1, M2, NW, NU, BV,
+                              (long long)(L.off_fg - L.off_W1) - (long long)(NS + 1) * M2, cr, P.alpha, true, AT, lda,
                               r * NW);
       }
     } else {
@@ -2565,16 +2593,24 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
           for (int i = tid; i < nl; i += blockDim.x) EXs[i] = Dp.ev_ex[i];
           build_cm_dense<NS>(T, Dp, xs + r * NW, hr, CMd, nA16, ldb);
           double* pwv = PWW + wave * 16 * 4 * P1;
+          // lane l < 16 holds the reference coordinates of its point of the next
+          // block, loaded while the current block is evaluated
+          double lamn[NS + 1];
+          auto load_lam = [&](int blk) {
+            const int f = min(blk + wave * 16 + lane, npts - 1);
+#pragma unroll
+            for (int k = 0; k <= NS; ++k) lamn[k] = gload(P.lam_ref + (size_t)(f % Q) * (NS + 1) + k);
+          };
+          if (lane < 16) load_lam(0);
           for (int blk = 0; blk < npts; blk += 64) {
             if (lane < 16) {
               const int f = min(blk + wave * 16 + lane, npts - 1);
               const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
-              const double* lam = P.lam_ref + (size_t)(f % Q) * (NS + 1);
               double var[NS + 1], phi = 0.0;
               for (int d = 1; d <= NS; ++d) var[d] = 0.0;
               for (int k = 0; k <= NS; ++k) {
-                phi += lam[k] * R[El<NS>::TAU + k];
-                for (int d = 0; d < NS; ++d) var[1 + d] += lam[k] * R[El<NS>::X + k * NS + d];
+                phi += lamn[k] * R[El<NS>::TAU + k];
+                for (int d = 0; d < NS; ++d) var[1 + d] += lamn[k] * R[El<NS>::X + k * NS + d];
               }
               var[0] = cr * (phi - tmid) / hr;
               for (int d = 0; d < NS; ++d) var[1 + d] = (var[1 + d] - XV[d]) / hr;
@@ -2585,8 +2621,24 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
                   a *= var[v];
                 }
               }
+              if (blk + 64 < npts) load_lam(blk + 64);
             }
             wave_sync();
+            // the incoming values and weights of the four points of this lane's
+            // row, loaded before the evaluation
+            double stv[4][NS + 1], wq[4];
+            if ((lane & 15) == 0) {
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int f = min(blk + wave * 16 + (lane >> 4) + 4 * rr, npts - 1);
+                const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+                const int q = f % Q;
+                const double* st = P.state + (size_t)(int)R[El<NS>::E] * (NS + 2) * Q;
+#pragma unroll
+                for (int c = 0; c <= NS; ++c) stv[rr][c] = gload(st + c * Q + q);
+                wq[rr] = gload(P.w_ref + q) * R[El<NS>::DET];
+              }
+            }
             double val[NS + 1][4];
             eval16_mfma<NS + 1, NS + 1>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, Dp.ev_nkv, EXs, pwv, P1, val);
             if ((lane & 15) == 0) {
@@ -2595,18 +2647,14 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
                 const int f = blk + wave * 16 + (lane >> 4) + 4 * rr;
                 if (f < npts) {
                   const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
-                  const int q = f % Q;
-                  const int e = (int)R[El<NS>::E];
-                  const double w = P.w_ref[q] * R[El<NS>::DET];
-                  const double* st = P.state + (size_t)e * (NS + 2) * Q;
-                  const double dv = cr * val[0][rr] - st[q];
+                  const double dv = cr * val[0][rr] - stv[rr][0];
                   double ds2 = 0.0, dsg = 0.0;
                   for (int d = 0; d < NS; ++d) {
-                    const double ds = val[1 + d][rr] - st[(1 + d) * Q + q];
+                    const double ds = val[1 + d][rr] - stv[rr][1 + d];
                     ds2 += ds * ds;
                     dsg += ds * R[El<NS>::GOLD + d];
                   }
-                  eta_loc += 0.5 * w * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
+                  eta_loc += 0.5 * wq[rr] * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
                 }
               }
             }
@@ -2684,19 +2732,31 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
         for (int i = tid; i < nl; i += blockDim.x) EXs[i] = Dp.ev_ex[i];
         build_cm_dense<NS>(T, Dp, xs + r * NW, hr, CMd, nA16, ldb);
         double* pwv = PWW + wave * 16 * 4 * P1;
+        // lane l < 16 holds the reference coordinates of its point of the next
+        // block, loaded while the current block is evaluated
+        double lamn[NS + 1];
+        auto load_lam = [&](int blk) {
+          const int f = min(blk + wave * 16 + lane, npts - 1);
+#pragma unroll
+          for (int k = 0; k <= NS; ++k) lamn[k] = gload(P.lam_ref + (size_t)(f % Q) * (NS + 1) + k);
+        };
+        if (lane < 16) load_lam(0);
         for (int blk = 0; blk < npts; blk += 64) {
           if (lane < 16) {
             const int f = min(blk + wave * 16 + lane, npts - 1);
             const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
             const int lV = (int)R[El<NS>::LV];
-            const double* lam = P.lam_ref + (size_t)(f % Q) * (NS + 1);
             double var[NS + 1], phi = 0.0;
             for (int d = 1; d <= NS; ++d) var[d] = 0.0;
             for (int k = 0; k <= NS; ++k) {
-              phi += lam[k] * R[El<NS>::TAU + k];
-              for (int d = 0; d < NS; ++d) var[1 + d] += lam[k] * R[El<NS>::X + k * NS + d];
+              phi += lamn[k] * R[El<NS>::TAU + k];
+              for (int d = 0; d < NS; ++d) var[1 + d] += lamn[k] * R[El<NS>::X + k * NS + d];
             }
-            phi += lam[lV] * dt;
+            double lv = lamn[0];
+#pragma unroll
+            for (int k = 1; k <= NS; ++k)
+              if (k == lV) lv = lamn[k];
+            phi += lv * dt;
             var[0] = cr * (phi - tmid) / hr;
             for (int d = 0; d < NS; ++d) var[1 + d] = (var[1 + d] - XV[d]) / hr;
             for (int v = 0; v <= NS; ++v) {
@@ -2706,6 +2766,7 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
                 a *= var[v];
               }
             }
+            if (blk + 64 < npts) load_lam(blk + 64);
           }
           wave_sync();
           double val[NS + 2][4];
