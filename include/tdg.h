@@ -252,9 +252,14 @@ int trefftz_layer_indicator(tdg_ctx* ctx, int32_t layer, int32_t p, double* eta,
  * feats, the network's predicted log eta_T(p) for p = 2..8 -> p_sel[tent] =
  * the smallest p <= p_max whose prediction is <= log_eta_tol (else p_max); a
  * tent whose realised eta_T exceeds eta_tol (if > 0) is solved again one
- * degree higher, up to p_max (accepted there), before anything is written.  w_bf16 = NULL: fixed p_max everywhere (the
- * fallback; p_sel is filled with p_max).  p_used (nullable) gets the degree
- * each tent was finally solved with, eta (nullable) its eta_T. */
+ * degree higher, up to p_max (accepted there), before anything is written.
+ * With a network the layer's tents are then drawn in decreasing chosen degree
+ * (index order inside a degree), so that the costliest start first and the
+ * cheap ones fill the end of the layer; the results do not depend on the
+ * order (the tents of a layer are independent).  w_bf16 = NULL: fixed p_max
+ * everywhere (the fallback; p_sel is filled with p_max), index order.  p_used
+ * (nullable) gets the degree each tent was finally solved with, eta (nullable)
+ * its eta_T. */
 int trefftz_layer_solve_adaptive(tdg_ctx* ctx, int32_t layer_begin, int32_t layer_end, const uint16_t* w_bf16,
                                  float log_eta_tol, double eta_tol, float* feats, int8_t* p_sel, int8_t* p_used,
                                  double* eta, tdg_stream stream);

@@ -76,6 +76,7 @@ struct tdg_ctx {
   KParams kp{};
   LdsPlan lp{};
   size_t w_ex = 0, w_partial = 0, w_out = 0, w_status = 0, w_sys = 0, w_ctr = 0;  // offsets in doubles inside WORK
+  size_t w_order = 0;  // the layers' queue orders (one int per tent)
   int persistent = 0, ncu = 256, resident = 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -553,7 +554,8 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   X->w_out = X->w_partial + 2 * X->nblocks_red + 32;
   X->w_status = X->w_out + 32;
   X->w_ctr = X->w_status + 32;
-  X->w_sys = X->w_ctr + ((X->tents.layer_ptr.size() + 1) / 2 + 31) / 32 * 32;
+  X->w_order = X->w_ctr + ((X->tents.layer_ptr.size() + 1) / 2 + 31) / 32 * 32;
+  X->w_sys = X->w_order + ((X->tents.V.size() + 1) / 2 + 31) / 32 * 32;
   {
     int64_t widest = 0;
     for (size_t l = 0; l + 1 < X->tents.layer_ptr.size(); ++l)
@@ -888,11 +890,16 @@ int trefftz_layer_solve_adaptive(tdg_ctx* X, int32_t layer_begin, int32_t layer_
   for (int l = layer_begin; l < layer_end; ++l) {
     const int t0 = (int)X->tents.layer_ptr[l];
     const int cnt = (int)(X->tents.layer_ptr[l + 1] - X->tents.layer_ptr[l]);
+    P.order = nullptr;
     if (w_bf16) {
+      // the chosen degrees, then the layer's queue in decreasing degree
+      int* order = (int*)((double*)X->dev[TDG_BUF_WORK] + X->w_order);
       if (launch_features(P, t0, cnt, feats, stream) ||
           launch_select((const unsigned short*)w_bf16, feats, t0, cnt, log_eta_tol, X->opts.p_max,
-                        (signed char*)p_sel, stream))
+                        (signed char*)p_sel, stream) ||
+          launch_order((const signed char*)p_sel, t0, cnt, X->opts.p_max, order, stream))
         return fail(TDG_EHIP, "degree selection launch failed");
+      P.order = order;
     } else if (launch_fill_i8((signed char*)p_sel + t0, (signed char)X->opts.p_max, cnt, stream)) {
       return fail(TDG_EHIP, "fill kernel launch failed");
     }
@@ -1152,6 +1159,21 @@ int tdg_debug_moment_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t*
   if (task1) std::copy(t.task1.begin(), t.task1.end(), task1);
   if (mt_ex) std::copy(t.mt_ex.begin(), t.mt_ex.end(), mt_ex);
   if (mt_map) std::copy(t.mt_map.begin(), t.mt_map.end(), mt_map);
+  return TDG_OK;
+}
+
+// Internal (tests): the queue order of layer `layer` as the last degree-adaptive
+// solve left it (out: the layer's tent count of tent indices); synchronises.
+int tdg_debug_queue_order(tdg_ctx* X, int32_t layer, int32_t* out, tdg_stream stream) {
+  if (!X || !out) return fail(TDG_EINVAL, "NULL argument");
+  if (!X->bound) return fail(TDG_ESTATE, "trefftz_bind first");
+  const int nl = (int)X->tents.layer_ptr.size() - 1;
+  if (layer < 0 || layer >= nl) return fail(TDG_EINVAL, "layer out of range");
+  const int64_t t0 = X->tents.layer_ptr[layer], cnt = X->tents.layer_ptr[layer + 1] - t0;
+  hipStream_t s = (hipStream_t)stream;
+  const int* order = (const int*)((double*)X->dev[TDG_BUF_WORK] + X->w_order);
+  HIP_OK(hipMemcpyAsync(out, order + t0, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
   return TDG_OK;
 }
 

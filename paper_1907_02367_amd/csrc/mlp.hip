@@ -310,6 +310,28 @@ __global__ __launch_bounds__(kMB) void select_degree_kernel(const unsigned short
 
 }  // namespace
 
+// The queue order of one layer: its tents by chosen degree, highest first, in
+// index order inside a degree (one wave; per degree a pass over the layer in
+// blocks of 64 places the matching tents by ballot and prefix count).  The
+// costliest tents start first, so the cheap ones fill the layer's tail.
+__global__ __launch_bounds__(64) void order_by_degree_kernel(const signed char* p_sel, int t0, int count, int pmax,
+                                                            int* order) {
+  const int lane = threadIdx.x;
+  int pos = 0;
+  for (int d = pmax; d >= 0; --d) {
+    for (int b = 0; b < count; b += 64) {
+      const int i = b + lane;
+      const int pi = i < count ? (int)p_sel[t0 + i] : 0;
+      // (degree 0 collects everything outside 1..pmax: the order is always a permutation)
+      const bool hit = i < count && (d == 0 ? (pi <= 0 || pi > pmax) : pi == d);
+      const unsigned long long m = __ballot(hit);
+      const int before = __popcll(m & ((1ull << lane) - 1ull));
+      if (hit) order[t0 + pos + before] = t0 + i;
+      pos += __popcll(m);
+    }
+  }
+}
+
 int launch_features(const KParams& P, int t0, int count, float* feats, void* stream) {
   if (count <= 0) return 0;
   hipStream_t s = (hipStream_t)stream;
@@ -319,6 +341,12 @@ int launch_features(const KParams& P, int t0, int count, float* feats, void* str
     hipLaunchKernelGGL(tent_features_kernel<2>, dim3(count), dim3(64), 0, s, P, t0, count, feats);
   else
     hipLaunchKernelGGL(tent_features_kernel<3>, dim3(count), dim3(64), 0, s, P, t0, count, feats);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_order(const signed char* p_sel, int t0, int count, int pmax, int* order, void* stream) {
+  if (count <= 0) return 0;
+  hipLaunchKernelGGL(order_by_degree_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, p_sel, t0, count, pmax, order);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -118,6 +118,9 @@ struct KParams {
   const double* tent_tt;
   const long long* bpt_off;  // ntents+1 offsets into gD
   const signed char* p_per_tent;  // nullable
+  // nullable: the order in which a layer's tents are drawn (queue position
+  // t0 + i -> tent order[t0 + i]; a permutation of the layer), costliest first
+  const int* order;
   int p_fixed;                    // > 0 and no p_per_tent: every tent at this degree
   // dynamic state
   double* state;  // ne * (n+2) * Q, element-major, then component, then point
@@ -197,6 +200,7 @@ int set_kernel_smem_limit(int n, size_t bytes);
 int launch_fill(double* p, double v, long long n, void* stream);
 int launch_fill_i8(signed char* p, signed char v, long long n, void* stream);
 int launch_features(const KParams& P, int t0, int count, float* feats, void* stream);
+int launch_order(const signed char* p_sel, int t0, int count, int pmax, int* order, void* stream);
 int launch_select(const unsigned short* wb, const float* feats, int t0, int count, float log_tol, int pmax,
                   signed char* p_sel, void* stream);
 int launch_norms(const KParams& P, int kind, const double* ex, double* partial, int nblocks, double* out, void* stream);

@@ -1266,30 +1266,19 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
     d4 acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
-    // the fields' chains interleaved (independent accumulators); the B operands
-    // of step ks + 1 are loaded before the products of step ks
-    auto load_b = [&](int ks, double (&bv)[NC]) {
-      const int b = ks * 4 + kq;
-      const bool sv = ks < nkvI;  // the first NV fields (degree <= p - 1) need fewer steps
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-        bv[c] = (b < nl && (c >= NV || sv)) ? CMd[((long long)c * nA16 + a) * ldb + b] : 0.0;
-    };
-    double bcur[NC];
-    load_b(0, bcur);
+    // the fields' chains interleaved (independent accumulators)
 #pragma unroll
     for (int ks = 0; ks < KMAX; ++ks) {
       if (ks < nk) {
-        double bnx[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) bnx[c] = 0.0;
-        if (ks + 1 < nk) load_b(ks + 1, bnx);
-        const bool sv = ks < nkvI;
+        const int b = ks * 4 + kq;
+        const bool sv = ks < nkvI;  // the first NV fields (degree <= p - 1) need fewer steps
+        double bv[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-          if (c >= NV || sv) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[ks], bcur[c], acc[c], 0, 0, 0);
+          bv[c] = (b < nl && (c >= NV || sv)) ? CMd[((long long)c * nA16 + a) * ldb + b] : 0.0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) bcur[c] = bnx[c];
+        for (int c = 0; c < NC; ++c)
+          if (c >= NV || sv) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[ks], bv[c], acc[c], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -2850,7 +2839,8 @@ template <int NS, int TPW, bool MIXED, bool MOM = false>
 __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L, int t0, int count, int* ctr) {
   extern __shared__ double lds[];
   if (ctr == nullptr) {
-    solve_tent<NS, TPW, MIXED, MOM>(P, L, t0 + blockIdx.x, lds);
+    const int qi = t0 + blockIdx.x;
+    solve_tent<NS, TPW, MIXED, MOM>(P, L, P.order ? P.order[qi] : qi, lds);
     return;
   }
   __shared__ int s_next;
@@ -2860,7 +2850,7 @@ __global__ __launch_bounds__(kBlock) void tent_layer_kernel(KParams P, LdsPlan L
     const int i = s_next;
     __syncthreads();
     if (i >= count) break;
-    solve_tent<NS, TPW, MIXED, MOM>(P, L, t0 + i, lds);
+    solve_tent<NS, TPW, MIXED, MOM>(P, L, P.order ? P.order[t0 + i] : t0 + i, lds);
     __syncthreads();
   }
 }

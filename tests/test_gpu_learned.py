@@ -174,7 +174,8 @@ def test_adaptive_sweep_matches_oracle_with_same_degrees():
     """A network that reads the patch size gives a spread of degrees; the
     library records the degree each tent was solved with (after any re-solves
     at higher degrees), and the oracle run with exactly those degrees must
-    agree to the FP64 bar."""
+    agree to the FP64 bar.  Each layer's tents are drawn in decreasing chosen
+    degree (the queue order the library builds after the degree choice)."""
     torch = _torch()
     pr = C.cfg2_plane_2d(m=8, p=5)
     o = oracle_for(pr)
@@ -213,6 +214,22 @@ def test_adaptive_sweep_matches_oracle_with_same_degrees():
     assert np.all(pu >= ps)
     assert np.all(et[pu < pr.p] <= eta_tol)
     assert np.all(et >= 0)
+    # the queue of every layer: a permutation of its tents, chosen degree not
+    # increasing along it, tent index increasing inside a degree
+    import ctypes
+    from paper_1907_02367_amd import tdg
+
+    fq = tdg.lib().tdg_debug_queue_order
+    fq.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    fq.restype = ctypes.c_int
+    lp = np.asarray(ctx.tents.layer_ptr)
+    for layer in range(ctx.tents.n_layers):
+        t0, t1 = int(lp[layer]), int(lp[layer + 1])
+        q = np.zeros(t1 - t0, np.int32)
+        assert fq(ctx._h, layer, q.ctypes.data, tdg._stream()) == 0
+        assert np.array_equal(np.sort(q), np.arange(t0, t1))
+        key = -ps[q].astype(np.int64) * (nt + 1) + q
+        assert np.all(np.diff(key) > 0)
     o.run(p_per_tent=pu)
     v, s, U = ctx.read_state()
     r_vs = rel_l2(np.concatenate([v.ravel(), s.ravel()]), np.concatenate([o.v.ravel(), o.sig.ravel()]))
