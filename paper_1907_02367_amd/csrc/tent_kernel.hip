@@ -350,9 +350,12 @@ __device__ inline bool panel_lu_solve(double* A, long long lda, int S, int nb, d
       }
     }
     for (int r = tid; r < R; r += blockDim.x) orig[r] = r;
+    if (tid == 0) piv[nb] = 0;  // zero-pivot flag
     __syncthreads();
-    for (int kk = 0; kk < nbb; ++kk) {
-      if (wave == 0) {
+    // the panel is factored by wave 0 alone (LDS order inside one wave, no
+    // workgroup barrier per column); the other waves wait at the next barrier
+    if (wave == 0) {
+      for (int kk = 0; kk < nbb; ++kk) {
         double best = -1.0;
         int bi = R;
         for (int r = kk + lane; r < R; r += 64) {
@@ -370,33 +373,38 @@ __device__ inline bool panel_lu_solve(double* A, long long lda, int S, int nb, d
             bi = oi;
           }
         }
-        if (lane == 0) piv[kk] = bi < R ? bi : kk;  // (a column of NaNs keeps its row)
-      }
-      __syncthreads();
-      const int pr = piv[kk];
-      if (pr != kk) {
-        for (int j = tid; j < nbb; j += blockDim.x) {
-          const double t = Pn[j * ldp + kk];
-          Pn[j * ldp + kk] = Pn[j * ldp + pr];
-          Pn[j * ldp + pr] = t;
+        const int pr = bi < R ? bi : kk;  // (a column of NaNs keeps its row); the same in every lane
+        wave_sync();
+        if (lane == 0) piv[kk] = pr;
+        if (pr != kk) {
+          for (int j = lane; j < nbb; j += 64) {
+            const double t = Pn[j * ldp + kk];
+            Pn[j * ldp + kk] = Pn[j * ldp + pr];
+            Pn[j * ldp + pr] = t;
+          }
+          if (lane == 0) {
+            const int t = orig[kk];
+            orig[kk] = orig[pr];
+            orig[pr] = t;
+          }
         }
-        if (tid == 0) {
-          const int t = orig[kk];
-          orig[kk] = orig[pr];
-          orig[pr] = t;
+        wave_sync();
+        const double pv = Pn[kk * ldp + kk];
+        if (pv == 0.0) {
+          if (lane == 0) piv[nb] = 1;
+          break;
         }
+        // one lane per row below the pivot: its multiplier, then its panel row
+        for (int r = kk + 1 + lane; r < R; r += 64) {
+          const double l = Pn[kk * ldp + r] / pv;
+          Pn[kk * ldp + r] = l;
+          for (int j = kk + 1; j < nbb; ++j) Pn[j * ldp + r] -= l * Pn[j * ldp + kk];
+        }
+        wave_sync();
       }
-      __syncthreads();
-      const double pv = Pn[kk * ldp + kk];
-      if (pv == 0.0) return false;
-      // one thread per row below the pivot: its multiplier, then its panel row
-      for (int r = kk + 1 + tid; r < R; r += blockDim.x) {
-        const double l = Pn[kk * ldp + r] / pv;
-        Pn[kk * ldp + r] = l;
-        for (int j = kk + 1; j < nbb; ++j) Pn[j * ldp + r] -= l * Pn[j * ldp + kk];
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    if (piv[nb]) return false;
     // U11 back to global memory (the diagonal block of the back substitution)
     for (int i = tid; i < nbb * nbb; i += blockDim.x) {
       const int r = i / nbb, j = i - r * nbb;
@@ -1292,6 +1300,91 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) val[c][r] += __shfl_xor(val[c][r], off, 64);
+}
+
+// eval16_mfma at two times per point: every point has 5 power rows (P1 each:
+// th at the bottom, xh_1..xh_3, th at the top), the products Y_c[pt][a] are
+// formed once, and valb[c] (c < NB, the bottom time) and valt[c] (all NC
+// fields, the top time) are its sums against L_a at either time.
+template <int NC, int NV, int NB>
+__device__ inline void eval16_mfma2(const double* CMd, int nA16, int ldb, int nl, int nat, const int* nks,
+                                    const int* nkv, const int* EX, const double* PWW, int P1,
+                                    double (&valb)[NB][4], double (&valt)[NC][4]) {
+  constexpr int KMAX = kEvalMaxSteps;
+  const int lane = threadIdx.x & 63;
+  const int pi = lane & 15, kq = lane >> 4;
+  const int ps = 5 * P1;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) valt[c][r] = 0.0;
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) valb[c][r] = 0.0;
+  const int nk0 = nks[0];
+  double rv[KMAX];
+  {
+    const double* pw = PWW + pi * ps;
+#pragma unroll
+    for (int ks = 0; ks < KMAX; ++ks) {
+      const int b = ks * 4 + kq;
+      rv[ks] = 0.0;
+      if (ks < nk0 && b < nl) {
+        const int eb = EX[b];
+        rv[ks] = pw[2 * P1 + (eb & 255)] * pw[3 * P1 + (eb >> 8)];
+      }
+    }
+  }
+  for (int I = 0; I < nat; ++I) {
+    const int a = I * 16 + pi;
+    const int ea = a < nl ? EX[a] : 0;
+    double Lb[4], Lt[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double* pw = PWW + (kq + 4 * r) * ps;
+      Lb[r] = a < nl ? pw[ea & 255] * pw[P1 + (ea >> 8)] : 0.0;
+      Lt[r] = a < nl ? pw[4 * P1 + (ea & 255)] * pw[P1 + (ea >> 8)] : 0.0;
+    }
+    const int nkvI = nkv[I];
+    const int nk = nks[I];
+    d4 acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KMAX; ++ks) {
+      if (ks < nk) {
+        const int b = ks * 4 + kq;
+        const bool sv = ks < nkvI;
+        double bv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          bv[c] = (b < nl && (c >= NV || sv)) ? CMd[((long long)c * nA16 + a) * ldb + b] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (c >= NV || sv) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[ks], bv[c], acc[c], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        valt[c][r] += acc[c][r] * Lt[r];
+        if (c < NB) valb[c < NB ? c : 0][r] += acc[c][r] * Lb[r];
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) valt[c][r] += __shfl_xor(valt[c][r], off, 64);
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) valb[c][r] += __shfl_xor(valb[c][r], off, 64);
 }
 
 // Dense coefficients CM_c[a][b] of the fields of group r's solution xs (3+1D):
@@ -2563,6 +2656,7 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
   int* runs = reinterpret_cast<int*>(W1 + (((NS + 2) * T.M + 3) & ~3));
   for (int i = tid; i < T.ntask1 * kTaskInts; i += blockDim.x) runs[i] = T.task1[i];
   const bool want_eta = P.indicator || !P.write_back || (P.eta_tol > 0.0 && p < P.pmax);
+  bool wb_done = false;  // the top values were formed with the indicator (into TMP)
   if (want_eta) {
     double eta_loc = 0.0;
     for (int r = 0; r < m; ++r) {
@@ -2572,6 +2666,107 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
       bool ev_mt = false;
       if constexpr (NS == 3) ev_mt = Dp.ev_nl > 0 && (long long)(L.off_fg - L.off_W1) >= ev_doubles(p, Dp.ev_nl);
       if constexpr (NS == 3) {
+        // One speed group, a write-back to follow and room for it: the top values
+        // are formed in the same pass (the products Y of the evaluation do not
+        // depend on the time coordinate) into the workgroup's global slot, which
+        // the solved system no longer needs, and copied to the stored values once
+        // the tent is accepted (the stored values stay the incoming ones until
+        // then, as a solve at a higher degree needs them).
+        const bool fuse = ev_mt && m == 1 && P.write_back && !L.A_in_lds &&
+                          (long long)npts * (NS + 2) <= P.work_stride &&
+                          (long long)(L.off_fg - L.off_W1) >= ev_doubles(p, Dp.ev_nl) + 4LL * 16 * (p + 1);
+        if (fuse) {
+          const int nl = Dp.ev_nl, nat = Dp.ev_nat, nA16 = 16 * nat, ldb = ev_ldb(nl), P1 = p + 1;
+          double* CMd = W1;
+          double* PWW = W1 + (long long)(NS + 2) * nA16 * ldb;
+          int* EXs = reinterpret_cast<int*>(PWW + 4 * 16 * 5 * P1);
+          double* TMP = A;  // (NS+2) x npts top values
+          __syncthreads();
+          for (int i = tid; i < nl; i += blockDim.x) EXs[i] = Dp.ev_ex[i];
+          build_cm_dense<NS>(T, Dp, xs + r * NW, hr, CMd, nA16, ldb);
+          double* pwv = PWW + wave * 16 * 5 * P1;
+          double lamn[NS + 1];
+          auto load_lam = [&](int blk) {
+            const int f = min(blk + wave * 16 + lane, npts - 1);
+#pragma unroll
+            for (int k = 0; k <= NS; ++k) lamn[k] = gload(P.lam_ref + (size_t)(f % Q) * (NS + 1) + k);
+          };
+          if (lane < 16) load_lam(0);
+          for (int blk = 0; blk < npts; blk += 64) {
+            if (lane < 16) {
+              // rows: th at the bottom, xh_1..xh_n, th at the top
+              const int f = min(blk + wave * 16 + lane, npts - 1);
+              const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+              const int lV = (int)R[El<NS>::LV];
+              double var[NS + 2], pho = 0.0;
+              for (int d = 1; d <= NS; ++d) var[d] = 0.0;
+              for (int k = 0; k <= NS; ++k) {
+                pho += lamn[k] * R[El<NS>::TAU + k];
+                for (int d = 0; d < NS; ++d) var[1 + d] += lamn[k] * R[El<NS>::X + k * NS + d];
+              }
+              double lv = lamn[0];
+#pragma unroll
+              for (int k = 1; k <= NS; ++k)
+                if (k == lV) lv = lamn[k];
+              var[0] = cr * (pho - tmid) / hr;
+              var[NS + 1] = cr * (pho + lv * dt - tmid) / hr;
+              for (int d = 0; d < NS; ++d) var[1 + d] = (var[1 + d] - XV[d]) / hr;
+              for (int v = 0; v <= NS + 1; ++v) {
+                double a = 1.0;
+                for (int e = 0; e < P1; ++e) {
+                  pwv[(lane * 5 + v) * P1 + e] = a;
+                  a *= var[v];
+                }
+              }
+              if (blk + 64 < npts) load_lam(blk + 64);
+            }
+            wave_sync();
+            double stv[4][NS + 1], wq[4];
+            if ((lane & 15) == 0) {
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int f = min(blk + wave * 16 + (lane >> 4) + 4 * rr, npts - 1);
+                const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+                const int q = f % Q;
+                const double* st = P.state + (size_t)(int)R[El<NS>::E] * (NS + 2) * Q;
+#pragma unroll
+                for (int c = 0; c <= NS; ++c) stv[rr][c] = gload(st + c * Q + q);
+                wq[rr] = gload(P.w_ref + q) * R[El<NS>::DET];
+              }
+            }
+            double valb[NS + 1][4], valt[NS + 2][4];
+            eval16_mfma2<NS + 2, NS + 1, NS + 1>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, Dp.ev_nkv, EXs, pwv, P1, valb,
+                                                 valt);
+            if ((lane & 15) == 0) {
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                const int f = blk + wave * 16 + (lane >> 4) + 4 * rr;
+                if (f < npts) {
+                  const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+                  const double dv = cr * valb[0][rr] - stv[rr][0];
+                  double ds2 = 0.0, dsg = 0.0;
+                  for (int d = 0; d < NS; ++d) {
+                    const double ds = valb[1 + d][rr] - stv[rr][1 + d];
+                    ds2 += ds * ds;
+                    dsg += ds * R[El<NS>::GOLD + d];
+                  }
+                  eta_loc += 0.5 * wq[rr] * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
+                  TMP[f] = cr * valt[0][rr];
+#pragma unroll
+                  for (int d = 0; d < NS; ++d) TMP[(long long)(1 + d) * npts + f] = valt[1 + d][rr];
+                  TMP[(long long)(NS + 1) * npts + f] = a0[r] + valt[NS + 1][rr];
+                  bool fin = true;
+#pragma unroll
+                  for (int c = 0; c < NS + 2; ++c) fin = fin && isfinite(valt[c][rr]);
+                  if (!fin) atomicOr(P.status, kStatNan);
+                }
+              }
+            }
+            wave_sync();
+          }
+          wb_done = true;
+          continue;
+        }
         if (ev_mt) {
           // fields at the bottom points on the matrix cores, 16 points per wave
           const int nl = Dp.ev_nl, nat = Dp.ev_nat, nA16 = 16 * nat, ldb = ev_ldb(nl), P1 = p + 1;
@@ -2702,6 +2897,22 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
     if (tid == 0 && P.dissip) P.dissip[tent] = eta;
     if (tid == 0 && P.p_used) P.p_used[tent] = (signed char)p;
     if (!P.write_back) return;
+    if (wb_done) {
+      // the accepted tent's top values (one group) from the global slot
+      const int npts = (s_goff[1] - s_goff[0]) * Q;
+      const double* TMP = A;
+      __threadfence_block();
+      for (int f = tid; f < npts; f += blockDim.x) {
+        const double* R = EL + s_gel[s_goff[0] + f / Q] * ELS;
+        const int q = f % Q;
+        double* st = P.state + (size_t)(int)R[El<NS>::E] * (NS + 2) * Q;
+#pragma unroll
+        for (int c = 0; c < NS + 2; ++c) st[(long long)c * Q + q] = TMP[(long long)c * npts + f];
+      }
+      __syncthreads();
+      if (tid == 0) P.tau[V] = tt;
+      break;
+    }
   } else if (tid == 0 && P.p_used) {
     P.p_used[tent] = (signed char)p;
   }

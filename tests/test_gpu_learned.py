@@ -238,6 +238,43 @@ def test_adaptive_sweep_matches_oracle_with_same_degrees():
     assert r_vs <= 1e-10 and r_U <= 1e-10
 
 
+def test_adaptive_3d_one_pass_matches_fixed_degree_solve():
+    """3+1D degree-adaptive sweep in moment mode: below p_max the indicator and
+    the tent's top values come from one pass of the matrix-core evaluation
+    (kept in the workgroup's global slot until the tent is accepted).  A plain
+    solve at the recorded degrees (write-back only, no indicator) must leave
+    the same stored values bit for bit."""
+    torch = _torch()
+    pr = C.cfg5_cube_3d(m=3, p=5, variant="b", regions=1, T=0.2)
+    pr.gamma = 0.4 * 0.8 ** 4  # (the jittered cube needs the lower edge slope to pitch)
+    ctx, xq, w = gpu_for(pr, gram_mode=1)
+    nt = ctx.tents.n_tents
+    # a network that reads the patch size: degrees 3..5 (weights exact in BF16)
+    d = OM.unpack(np.zeros(OM.N_PARAM))
+    d = {k: v.copy() for k, v in d.items()}
+    d["W1"][0, 2] = 4.0
+    d["W2"][0, 0] = 1.0
+    d["W3"][:, 0] = 10.0
+    d["b3"][:] = [100.0, -7.0, -7.5, -100.0, -100.0, -100.0, -100.0]
+    bits = OM.bf16_bits(OM.pack(d).astype(np.float32))
+    assert np.array_equal(OM.bf16_value(bits), OM.pack(d))
+    wb = _dev_bits(bits)
+    feats = torch.zeros((nt, 8), dtype=torch.float32, device="cuda")
+    p_sel = torch.zeros(nt, dtype=torch.int8, device="cuda")
+    p_used = torch.zeros(nt, dtype=torch.int8, device="cuda")
+    eta = torch.zeros(nt, dtype=torch.float64, device="cuda")
+    ctx.layer_solve_adaptive(wb, 0.0, 1e-7, feats, p_sel, p_used, eta)
+    ctx.status()
+    ps, pu = p_sel.cpu().numpy(), p_used.cpu().numpy()
+    say(f"  3D selected degrees {np.bincount(ps, minlength=6)[2:]}, used {np.bincount(pu, minlength=6)[2:]}")
+    assert (pu < pr.p).sum() > 0 and len(set(pu.tolist())) >= 2
+    ref, _, _ = gpu_for(pr, gram_mode=1)
+    ref.layer_solve(p_per_tent=p_used)
+    ref.status()
+    for a, b in zip(ctx.read_state(), ref.read_state()):
+        assert np.array_equal(a, b)
+
+
 def test_adaptive_without_network_is_fixed_pmax():
     torch = _torch()
     pr = C.cfg2_plane_2d(m=6, p=4)

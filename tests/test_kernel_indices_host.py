@@ -229,6 +229,22 @@ def test_matrix_core_evaluation_indices_3d(p_max, gram_mode):
         pww = 4 * 16 * 4 * P1
         if dense + pww + (nl + 1) // 2 + 1 > w1:
             continue  # the kernel keeps the VALU evaluation at this degree (its fit test)
+        # the evaluation at two times (indicator and write-back in one pass):
+        # 5 power rows per point, its fit test, and every power read inside the
+        # wave's rows (R at rows 2, 3 of point l%16; L at rows 0, 1 and 4 of the
+        # points l/16 + 4r)
+        pww5 = 4 * 16 * 5 * P1
+        if dense + pww5 + (nl + 1) // 2 + 1 <= w1:
+            lane = np.arange(64)
+            e = np.array([int(x) for x in ex])
+            for r in range(4):
+                pt = (lane >> 4) + 4 * r
+                for row in (0, 1, 4):
+                    addr = pt[:, None] * 5 * P1 + row * P1 + (e[None, :] & 255 if row != 1 else e[None, :] >> 8)
+                    assert addr.max() < 16 * 5 * P1
+            for row in (2, 3):
+                addr = (lane & 15)[:, None] * 5 * P1 + row * P1 + (e[None, :] & 255 if row == 2 else e[None, :] >> 8)
+                assert addr.max() < 16 * 5 * P1
         # reads of eval16_mfma: coefficients, powers (pt <= 15, exponents <= p)
         lane = np.arange(64)
         for I in range(nat):
