@@ -1305,12 +1305,12 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
 // eval16_mfma at two times per point: every point has 5 power rows (P1 each:
 // th at the bottom, xh_1..xh_3, th at the top), the products Y_c[pt][a] are
 // formed once, and valb[c] (c < NB, the bottom time) and valt[c] (all NC
-// fields, the top time) are its sums against L_a at either time.
-template <int NC, int NV, int NB>
+// fields, the top time) are its sums against L_a at either time.  KMAX >= the
+// step count of tile 0.
+template <int NC, int NV, int NB, int KMAX>
 __device__ inline void eval16_mfma2(const double* CMd, int nA16, int ldb, int nl, int nat, const int* nks,
                                     const int* nkv, const int* EX, const double* PWW, int P1,
                                     double (&valb)[NB][4], double (&valt)[NC][4]) {
-  constexpr int KMAX = kEvalMaxSteps;
   const int lane = threadIdx.x & 63;
   const int pi = lane & 15, kq = lane >> 4;
   const int ps = 5 * P1;
@@ -2084,9 +2084,35 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
         const double cr = gc[r], hr = gh[r];
         const int npts = nf * Q;
         for (int i = tid; i < (NS + 1) * (M2 + M1); i += blockDim.x) NU[i] = 0.0;
+        // 3+1D: the geometric moments on the matrix cores, as the top moments of
+        // the elements (tiles of (w L)^T R), face by face (the normal is constant
+        // on a face: after its last chunk nu += C_f, nu_d += n_d C_f); chunks
+        // then hold points of one face only
+        bool fmt = false;
+        if constexpr (NS == 3) fmt = Dp.mt_ntile > 0;
+        const int fwave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int fnsl = (Dp.mt_ntile + 3) >> 2;
+        unsigned ftex[kMomTileSlots];
+        d4 facc[kMomTileSlots];
+#pragma unroll
+        for (int sl = 0; sl < kMomTileSlots; ++sl) {
+          const int t = fwave + 4 * sl;
+          ftex[sl] = (fmt && t < Dp.mt_ntile) ? (unsigned)Dp.mt_ex[t * 16 + (lane & 15)] : 0u;
+          facc[sl] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+        const int cpf = fmt ? (Q + PCH - 1) / PCH : 1;  // chunks per face (tile path)
+        const int nchunk = fmt ? nf * cpf : (npts + PCH - 1) / PCH;
         __syncthreads();
-        for (int f0 = 0; f0 < npts; f0 += PCH) {
-          const int nc = min(PCH, npts - f0);
+        for (int cc = 0; cc < nchunk; ++cc) {
+          const int f0 = fmt ? (cc / cpf) * Q + (cc % cpf) * PCH : cc * PCH;
+          const int nc = fmt ? min(PCH, Q - (cc % cpf) * PCH) : min(PCH, npts - f0);
+          const int nc4 = (nc + 3) & ~3;
+          if (fmt)
+            for (int pt = nc + tid; pt < nc4; pt += blockDim.x) {
+              // points past the chunk up to a multiple of 4: weight 0, coordinates 0
+              PW[pt] = 0.0;
+              for (int v = 0; v <= NS; ++v) PV[pt * (NS + 1) + v] = 0.0;
+            }
           for (int pt = tid; pt < nc; pt += blockDim.x) {
             const int fi = s_fl[s_foff[r] + (f0 + pt) / Q];
             const int q = (f0 + pt) % Q;
@@ -2109,7 +2135,7 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
             for (int d = 0; d < NS; ++d) PV[pt * (NS + 1) + 1 + d] = (y[d] - XV[d]) / hr;
           }
           __syncthreads();
-          for (int i = tid; i < nc * (NS + 1); i += blockDim.x) {
+          for (int i = tid; i < (fmt ? nc4 : nc) * (NS + 1); i += blockDim.x) {
             const int pt = i / (NS + 1), v = i % (NS + 1);
             const double x = PV[pt * (NS + 1) + v];
             double a = 1.0;
@@ -2120,9 +2146,28 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
             }
           }
           __syncthreads();
+          if (fmt) {
+            // geometric moments on the matrix cores (every wave runs wave 0's slot
+            // count; a slot past the wave's tiles has exponents 0 and is not folded)
+            for (int ks = 0; ks < (nc4 >> 2); ++ks) {
+              const int pt = ks * 4 + (lane >> 4);
+              const double* pw = POWT + pt * (NS + 1) * E2;
+              const double w = PW[pt];
+#pragma unroll
+              for (int sl = 0; sl < kMomTileSlots; ++sl) {
+                if (sl < fnsl) {
+                  const unsigned ex = ftex[sl];
+                  const double a = w * (pw[ex & 31u] * pw[E2 + ((ex >> 5) & 31u)]);
+                  const double b = pw[2 * E2 + ((ex >> 10) & 31u)] * pw[3 * E2 + ((ex >> 15) & 31u)];
+                  facc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, facc[sl], 0, 0, 0);
+                }
+              }
+            }
+          }
           // geometric moments (w, w n_d) over the moment monomials
 #pragma unroll
           for (int sl = 0; sl < kTaskSlots; ++sl) {
+            if (fmt) break;
             if (tid + sl * (int)blockDim.x >= T.ntask2) break;
             const unsigned w0 = RT.w0[sl];
             int e[NS];
@@ -2213,6 +2258,32 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
             }
           }
           __syncthreads();
+          if (fmt && cc % cpf == cpf - 1) {
+            // the face's tiles into the moments (each moment index belongs to one
+            // tile entry: no two lanes or waves write the same word)
+            const double* G0 = FG + s_fl[s_foff[r] + cc / cpf] * FGS;
+            double nrm[NS];
+#pragma unroll
+            for (int d = 0; d < NS; ++d) nrm[d] = G0[2 + d];
+#pragma unroll
+            for (int sl = 0; sl < kMomTileSlots; ++sl) {
+              const int t = fwave + 4 * sl;
+              if (t < Dp.mt_ntile) {
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4) {
+                  const int b = Dp.mt_map[t * 256 + ((lane >> 4) + 4 * e4) * 16 + (lane & 15)];
+                  if (b >= 0) {
+                    const double c = facc[sl][e4];
+                    NU[b] += c;
+#pragma unroll
+                    for (int d = 0; d < NS; ++d) NU[(1 + d) * M2 + b] += nrm[d] * c;
+                  }
+                }
+              }
+              facc[sl] = d4{0.0, 0.0, 0.0, 0.0};
+            }
+            __syncthreads();
+          }
         }
         for (int i = tid; i < NW; i += blockDim.x) {
           double b = 0.0;
@@ -2672,24 +2743,36 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
         // the solved system no longer needs, and copied to the stored values once
         // the tent is accepted (the stored values stay the incoming ones until
         // then, as a solve at a higher degree needs them).
-        const bool fuse = ev_mt && m == 1 && P.write_back && !L.A_in_lds &&
+        constexpr int kFuseSteps = 9;  // tile-0 steps of the one-pass evaluation (p <= 7)
+        const bool fuse = ev_mt && m == 1 && P.write_back && !L.A_in_lds && Dp.ev_nks[0] <= kFuseSteps &&
                           (long long)npts * (NS + 2) <= P.work_stride &&
-                          (long long)(L.off_fg - L.off_W1) >= ev_doubles(p, Dp.ev_nl) + 4LL * 16 * (p + 1);
+                          (long long)(L.off_fg - L.off_W1) >= ev_doubles(p, Dp.ev_nl) + 4LL * 16 * (p + 1) + 4 * 16 * 5;
         if (fuse) {
           const int nl = Dp.ev_nl, nat = Dp.ev_nat, nA16 = 16 * nat, ldb = ev_ldb(nl), P1 = p + 1;
           double* CMd = W1;
           double* PWW = W1 + (long long)(NS + 2) * nA16 * ldb;
-          int* EXs = reinterpret_cast<int*>(PWW + 4 * 16 * 5 * P1);
+          double* SVW = PWW + 4 * 16 * 5 * P1;  // per wave and point: incoming v, sigma and the weight
+          int* EXs = reinterpret_cast<int*>(SVW + 4 * 16 * 5);
           double* TMP = A;  // (NS+2) x npts top values
           __syncthreads();
           for (int i = tid; i < nl; i += blockDim.x) EXs[i] = Dp.ev_ex[i];
           build_cm_dense<NS>(T, Dp, xs + r * NW, hr, CMd, nA16, ldb);
           double* pwv = PWW + wave * 16 * 5 * P1;
-          double lamn[NS + 1];
+          double* svw = SVW + wave * 16 * 5;
+          // lane l < 16 holds the reference coordinates, incoming values and
+          // weight of its point of the next block, loaded while the current
+          // block is evaluated
+          double lamn[NS + 1], stn[NS + 2];
           auto load_lam = [&](int blk) {
             const int f = min(blk + wave * 16 + lane, npts - 1);
+            const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
+            const int q = f % Q;
+            const double* st = P.state + (size_t)(int)R[El<NS>::E] * (NS + 2) * Q;
 #pragma unroll
-            for (int k = 0; k <= NS; ++k) lamn[k] = gload(P.lam_ref + (size_t)(f % Q) * (NS + 1) + k);
+            for (int k = 0; k <= NS; ++k) lamn[k] = gload(P.lam_ref + (size_t)q * (NS + 1) + k);
+#pragma unroll
+            for (int c = 0; c <= NS; ++c) stn[c] = gload(st + c * Q + q);
+            stn[NS + 1] = gload(P.w_ref + q) * R[El<NS>::DET];
           };
           if (lane < 16) load_lam(0);
           for (int blk = 0; blk < npts; blk += 64) {
@@ -2718,39 +2801,29 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
                   a *= var[v];
                 }
               }
+#pragma unroll
+              for (int c = 0; c < NS + 2; ++c) svw[lane * 5 + c] = stn[c];
               if (blk + 64 < npts) load_lam(blk + 64);
             }
             wave_sync();
-            double stv[4][NS + 1], wq[4];
-            if ((lane & 15) == 0) {
-#pragma unroll
-              for (int rr = 0; rr < 4; ++rr) {
-                const int f = min(blk + wave * 16 + (lane >> 4) + 4 * rr, npts - 1);
-                const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
-                const int q = f % Q;
-                const double* st = P.state + (size_t)(int)R[El<NS>::E] * (NS + 2) * Q;
-#pragma unroll
-                for (int c = 0; c <= NS; ++c) stv[rr][c] = gload(st + c * Q + q);
-                wq[rr] = gload(P.w_ref + q) * R[El<NS>::DET];
-              }
-            }
             double valb[NS + 1][4], valt[NS + 2][4];
-            eval16_mfma2<NS + 2, NS + 1, NS + 1>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, Dp.ev_nkv, EXs, pwv, P1, valb,
-                                                 valt);
+            eval16_mfma2<NS + 2, NS + 1, NS + 1, kFuseSteps>(CMd, nA16, ldb, nl, nat, Dp.ev_nks, Dp.ev_nkv, EXs, pwv,
+                                                              P1, valb, valt);
             if ((lane & 15) == 0) {
 #pragma unroll
               for (int rr = 0; rr < 4; ++rr) {
                 const int f = blk + wave * 16 + (lane >> 4) + 4 * rr;
                 if (f < npts) {
                   const double* R = EL + s_gel[s_goff[r] + f / Q] * ELS;
-                  const double dv = cr * valb[0][rr] - stv[rr][0];
+                  const double* sv = svw + ((lane >> 4) + 4 * rr) * 5;
+                  const double dv = cr * valb[0][rr] - sv[0];
                   double ds2 = 0.0, dsg = 0.0;
                   for (int d = 0; d < NS; ++d) {
-                    const double ds = valb[1 + d][rr] - stv[rr][1 + d];
+                    const double ds = valb[1 + d][rr] - sv[1 + d];
                     ds2 += ds * ds;
                     dsg += ds * R[El<NS>::GOLD + d];
                   }
-                  eta_loc += 0.5 * wq[rr] * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
+                  eta_loc += 0.5 * sv[NS + 1] * (ic2 * dv * dv + ds2 - 2.0 * dv * dsg);
                   TMP[f] = cr * valt[0][rr];
 #pragma unroll
                   for (int d = 0; d < NS; ++d) TMP[(long long)(1 + d) * npts + f] = valt[1 + d][rr];
