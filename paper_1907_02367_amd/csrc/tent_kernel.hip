@@ -350,12 +350,9 @@ __device__ inline bool panel_lu_solve(double* A, long long lda, int S, int nb, d
       }
     }
     for (int r = tid; r < R; r += blockDim.x) orig[r] = r;
-    if (tid == 0) piv[nb] = 0;  // zero-pivot flag
     __syncthreads();
-    // the panel is factored by wave 0 alone (LDS order inside one wave, no
-    // workgroup barrier per column); the other waves wait at the next barrier
-    if (wave == 0) {
-      for (int kk = 0; kk < nbb; ++kk) {
+    for (int kk = 0; kk < nbb; ++kk) {
+      if (wave == 0) {
         double best = -1.0;
         int bi = R;
         for (int r = kk + lane; r < R; r += 64) {
@@ -373,38 +370,33 @@ __device__ inline bool panel_lu_solve(double* A, long long lda, int S, int nb, d
             bi = oi;
           }
         }
-        const int pr = bi < R ? bi : kk;  // (a column of NaNs keeps its row); the same in every lane
-        wave_sync();
-        if (lane == 0) piv[kk] = pr;
-        if (pr != kk) {
-          for (int j = lane; j < nbb; j += 64) {
-            const double t = Pn[j * ldp + kk];
-            Pn[j * ldp + kk] = Pn[j * ldp + pr];
-            Pn[j * ldp + pr] = t;
-          }
-          if (lane == 0) {
-            const int t = orig[kk];
-            orig[kk] = orig[pr];
-            orig[pr] = t;
-          }
-        }
-        wave_sync();
-        const double pv = Pn[kk * ldp + kk];
-        if (pv == 0.0) {
-          if (lane == 0) piv[nb] = 1;
-          break;
-        }
-        // one lane per row below the pivot: its multiplier, then its panel row
-        for (int r = kk + 1 + lane; r < R; r += 64) {
-          const double l = Pn[kk * ldp + r] / pv;
-          Pn[kk * ldp + r] = l;
-          for (int j = kk + 1; j < nbb; ++j) Pn[j * ldp + r] -= l * Pn[j * ldp + kk];
-        }
-        wave_sync();
+        if (lane == 0) piv[kk] = bi < R ? bi : kk;  // (a column of NaNs keeps its row)
       }
+      __syncthreads();
+      const int pr = piv[kk];
+      if (pr != kk) {
+        for (int j = tid; j < nbb; j += blockDim.x) {
+          const double t = Pn[j * ldp + kk];
+          Pn[j * ldp + kk] = Pn[j * ldp + pr];
+          Pn[j * ldp + pr] = t;
+        }
+        if (tid == 0) {
+          const int t = orig[kk];
+          orig[kk] = orig[pr];
+          orig[pr] = t;
+        }
+      }
+      __syncthreads();
+      const double pv = Pn[kk * ldp + kk];
+      if (pv == 0.0) return false;
+      // one thread per row below the pivot: its multiplier, then its panel row
+      for (int r = kk + 1 + tid; r < R; r += blockDim.x) {
+        const double l = Pn[kk * ldp + r] / pv;
+        Pn[kk * ldp + r] = l;
+        for (int j = kk + 1; j < nbb; ++j) Pn[j * ldp + r] -= l * Pn[j * ldp + kk];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (piv[nb]) return false;
     // U11 back to global memory (the diagonal block of the back substitution)
     for (int i = tid; i < nbb * nbb; i += blockDim.x) {
       const int r = i / nbb, j = i - r * nbb;
