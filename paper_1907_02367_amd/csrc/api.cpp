@@ -201,7 +201,7 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         };
         L.off_x = take(L.S + kMaxGroups);
         L.off_el = take((long long)maxpatch * L.ELS);
-        L.off_misc = take(5 * kMaxGroups + 24 + (long long)kMaxGroups * L.NWP);
+        L.off_misc = take(5 * kMaxGroups + 24 + (long long)X->max_groups * L.NWP);
         L.off_pt = take((long long)pch * (2 * (n + 1) + 1 + (n + 2) + n + 1));
         L.off_pow = take(pw_sz);
         L.off_mono = 0;
@@ -291,7 +291,7 @@ int plan_lds(tdg_ctx* X, int forced_pch = 0) {
         };
         L.off_x = take(L.S + kMaxGroups);
         L.off_el = take((long long)maxpatch * L.ELS);
-        L.off_misc = take(5 * kMaxGroups + 24 + (long long)kMaxGroups * L.NWP);
+        L.off_misc = take(5 * kMaxGroups + 24 + (long long)X->max_groups * L.NWP);
         L.off_pt = take(pt_sz);
         L.off_pow = take(pw_sz);
         L.off_mono = take(mono_sz(pmax, pch));
@@ -424,7 +424,7 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
     }
     X->max_groups = std::max(X->max_groups, (int)cs.size());
   }
-  if (X->max_groups > kMaxGroups) return fail(TDG_EINVAL, "more than 8 wave speeds in one vertex patch");
+  if (X->max_groups > kMaxGroups) return fail(TDG_EINVAL, "more than 32 wave speeds in one vertex patch");
   // boundary points: replay the front
   {
     const int Q = X->quad.Q;

@@ -22,7 +22,7 @@ constexpr int kTaskSlots1 = 2;  // tasks over the monomials of degree <= p, per 
 // the moments of all products form the 16x16 tiles of (w L)^T R, only the tiles
 // with a product of degree <= 2p-2 are formed, at most kMomTileSlots per wave
 constexpr int kMomTileSlots = 6;
-constexpr int kMaxGroups = 8;    // speed groups inside one tent (Sec. 4.2)
+constexpr int kMaxGroups = 32;   // speed groups inside one tent (Sec. 4.2)
 constexpr int kMaxPatch = 64;    // elements in one vertex patch
 constexpr int kMaxFaces = 64;    // Dirichlet facets containing one vertex
 constexpr int kBlock = 256;      // threads per workgroup of the tent kernels

@@ -1429,7 +1429,7 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
   double* r0 = A00 + kMaxGroups;
   double* a0 = r0 + kMaxGroups;
   double* fsc = a0 + kMaxGroups;  // 24: face measure, normal, simplex vertices
-  double* A0 = fsc + 24;          // kMaxGroups x NWP
+  double* A0 = fsc + 24;          // (groups of the mesh's largest patch) x NWP
   // system: LDS or this workgroup's slot of the global scratch
   const long long lda = L.lda;
   double* A = L.A_in_lds ? lds + L.off_A : P.work + (long long)blockIdx.x * P.work_stride;
@@ -1597,11 +1597,12 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
     if (tid == 0) atomicOr(P.status, s_err ? s_err : kStatSize);
     return;
   }
-  {
+  // group diameters h_r (eq. 3.3 with the group's speed), eight groups per pass
+  for (int r0g = 0; r0g < m; r0g += 8) {
     const int nvert = npatch * (NS + 1) + 1;
     const long long npair = (long long)nvert * (nvert - 1) / 2;
-    double hloc[kMaxGroups];
-    for (int r = 0; r < kMaxGroups; ++r) hloc[r] = 0.0;
+    double hloc[8];
+    for (int r = 0; r < 8; ++r) hloc[r] = 0.0;
     for (long long pi = tid; pi < npair; pi += blockDim.x) {
       int a = 0;
       long long rem = pi;
@@ -1631,12 +1632,12 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
       for (int d = 0; d < NS; ++d) dx2 += (xa[d] - xb[d]) * (xa[d] - xb[d]);
       const double dtt = ta - tbv;
 #pragma unroll
-      for (int r = 0; r < kMaxGroups; ++r)
-        if (r < m) hloc[r] = fmax(hloc[r], sqrt(dx2 + gc[r] * gc[r] * dtt * dtt));
+      for (int r = 0; r < 8; ++r)
+        if (r0g + r < m) hloc[r] = fmax(hloc[r], sqrt(dx2 + gc[r0g + r] * gc[r0g + r] * dtt * dtt));
     }
 #pragma unroll
-    for (int r = 0; r < kMaxGroups; ++r)
-      if (r < m) atomic_max_nonneg(&gh[r], hloc[r]);
+    for (int r = 0; r < 8; ++r)
+      if (r0g + r < m) atomic_max_nonneg(&gh[r0g + r], hloc[r]);
   }
   // mixed precision: FP32 Gram first; faces kept apart (AF) for the FP64 residual
   double* AF = nullptr;
@@ -1654,7 +1655,7 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
     A[i] = 0.0;
     if constexpr (MIXED) AF[i] = 0.0;
   }
-  for (int i = tid; i < kMaxGroups * NWP; i += blockDim.x) A0[i] = 0.0;
+  for (int i = tid; i < m * NWP; i += blockDim.x) A0[i] = 0.0;
   if (tid < kMaxGroups) {
     A00[tid] = 0.0;
     r0[tid] = 0.0;
@@ -2428,13 +2429,13 @@ __device__ __attribute__((always_inline)) void solve_tent(const KParams& P, cons
         if (e == e1) g1 = (int)EL[i * ELS + El<NS>::GRP];
         if (e == e2) g2 = (int)EL[i * ELS + El<NS>::GRP];
       }
-      s_piv = g1 * 16 + g2;
+      s_piv = g1 * kMaxGroups + g2;  // (both below kMaxGroups)
     }
     __syncthreads();
     const double meas = fsc[0];
     double nrm[NS];
     for (int d = 0; d < NS; ++d) nrm[d] = fsc[1 + d];
-    const int ga = s_piv / 16, gb = s_piv % 16;
+    const int ga = s_piv / kMaxGroups, gb = s_piv % kMaxGroups;
     // g_N of a Neumann face: after the tent's Dirichlet faces in the boundary data
     const long long goff = P.bpt_off[tent] + (long long)(nbf + f - nif) * Q;
     for (int q0 = 0; q0 < Q; q0 += PCI) {

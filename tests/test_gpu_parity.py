@@ -48,6 +48,10 @@ CASES = {
     "2d_p8_m4": lambda: (C.cfg2_plane_2d(m=4, p=8), None, None),
     "3d_p5_b": lambda: (C.cfg5_cube_3d(m=2, p=5, variant="b"), None, None),
     "3d_p3_a_8groups_global_system": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="a", regions=2), None, None),
+    # speeds drawn per element (the literal reading): the central vertex's tent
+    # has 24 speed groups, a system of 24 x NW unknowns
+    "3d_p2_e_per_element_speeds": lambda: (C.cfg5_cube_3d(m=2, p=2, variant="e", T=0.15), None, None),
+    "3d_p3_e_per_element_speeds": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="e", T=0.15), None, None),
     "3d_p8_b_multipass_gram": lambda: (C.cfg5_cube_3d(m=2, p=8, variant="b"), None, None),
     # the largest degree with tables (p = 10)
     "1d_p10_max_degree": lambda: (C.cfg1_standing_1d(n_elems=8, p=10), None, None),

@@ -111,7 +111,9 @@ def cfg5_cube_3d(m: int = 25, p: int = 8, seed: int = 0, T: float = 0.5,
     """3+1D: unit cube, m^3 cubes x 6 Kuhn tetrahedra (m = 25: 93,750 tets),
     jittered, aligned with the planes of a regions^3 partition.
     Variant a: c_r ~ U[1,2] per region, U0 = sin sin sin, v0 = 0, homogeneous
-    Dirichlet.  Variant b: c = 1.5 everywhere, exact standing wave."""
+    Dirichlet.  Variant b: c = 1.5 everywhere, exact standing wave.  Variant e:
+    c_e ~ U[1,2] per element (every tent has as many speed groups as patch
+    elements), data as variant a."""
     planes = [k / regions for k in range(1, regions)]
     coords, elems = M.kuhn_cube(m, 0.15, seed, planes)
     cent = M.element_centroids(coords, elems)
@@ -120,6 +122,11 @@ def cfg5_cube_3d(m: int = 25, p: int = 8, seed: int = 0, T: float = 0.5,
         cr = rng.uniform(1.0, 2.0, size=(regions,) * 3)
         ix = np.clip((cent * regions).astype(int), 0, regions - 1)
         c = cr[ix[:, 0], ix[:, 1], ix[:, 2]]
+        data = F.SinProduct()
+        exact = False
+    elif variant == "e":
+        rng = np.random.default_rng(seed + 13)
+        c = rng.uniform(1.0, 2.0, size=len(elems))
         data = F.SinProduct()
         exact = False
     else:
