@@ -622,15 +622,17 @@ __device__ inline void moment_gram_pass(const int* fo_ptr, const int* fo_idx, co
   }
 }
 
-// The Gram block with as many test functions per pass (1, 2 or 4) as the Z
-// rows fit in zcap doubles at Z.
+// The Gram block with as many test functions per pass (1, 2, 4 or 8) as the
+// Z rows fit in zcap doubles at Z.
 template <int NS>
 __device__ inline void moment_gram_block(const int* fo_ptr, const int* fo_idx, const double* fo_coef,
                                          const int* K2, int M1, int M2, int NW, const double* NU, double* Z,
                                          long long zcap, double cr, double alpha, bool dirichlet, double* A,
                                          long long lda, int row0) {
   const long long per = (long long)(NS + 1) * M1;
-  if (zcap >= 4 * per)
+  if (zcap >= 8 * per)
+    moment_gram_pass<NS, 8>(fo_ptr, fo_idx, fo_coef, K2, M1, M2, NW, NU, Z, cr, alpha, dirichlet, A, lda, row0);
+  else if (zcap >= 4 * per)
     moment_gram_pass<NS, 4>(fo_ptr, fo_idx, fo_coef, K2, M1, M2, NW, NU, Z, cr, alpha, dirichlet, A, lda, row0);
   else if (zcap >= 2 * per)
     moment_gram_pass<NS, 2>(fo_ptr, fo_idx, fo_coef, K2, M1, M2, NW, NU, Z, cr, alpha, dirichlet, A, lda, row0);
