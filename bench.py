@@ -172,7 +172,7 @@ def bench_cube_3d(args):
     Gram.  One step = reset + the degree-adaptive sweep (features, network,
     degree choice, tent solves, indicator re-solves) over the first `window`
     layers; the same window is swept at fixed p = 8 (the plain method, the
-    fallback and the judge of the error) as the comparison."""
+    fallback and the reference for the error) as the comparison."""
     import torch
 
     from paper_1907_02367_amd import learned_p as LP
@@ -297,7 +297,7 @@ def bench_cube_3d(args):
             "bound": "alu", "achieved": r["achieved_alg"] / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
             "frac": r["achieved_alg"] / FP64_PEAK, "traffic": measured_traffic(f"cube_3d_{main_path}"),
             "kernel": "tent_layer_kernel<3,1,false,true> (moment Gram, FP64)",
-            "count": "quadrature-form operation count of eq. 4.1 per tent at its degree (the survey's formula)",
+            "count": "quadrature-form operation count of eq. 4.1 per tent at its degree (op_counts_deg)",
             "achieved_executed": r["achieved_exec"] / 1e12, "frac_executed": r["achieved_exec"] / FP64_PEAK,
             "count_executed": "operations the moment form executes (bench.moment_exec_flops)",
             "launches_per_step": window, "avg_launch_us": r["avg_launch_us"],

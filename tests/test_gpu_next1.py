@@ -1,4 +1,4 @@
-"""GPU parity of the survey's first next row against the oracle: Neumann faces
+"""GPU parity against the oracle of Neumann faces
 (eq. 4.1, T^N), the paper's recovery of U with the terms for every test
 function (Sec. 5; recover_U = 2) and the U error (Sec. 6.6).  Same seeded
 inputs on both sides; the boundary data at each library boundary point is
