@@ -90,6 +90,28 @@ __device__ inline void block_sum2(double& a, double& b, double* scratch) {
   __syncthreads();
 }
 
+// A double from another lane of the same row of 16 lanes by a DPP control
+// (register-to-register, no LDS): the two 32-bit halves move separately.
+template <int CTRL>
+__device__ inline double dpp_row(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over each row of 16 lanes, every lane of the row receiving it: the pairs
+// of the butterfly over lane bits 0..3 (quad_perm [1,0,3,2] and [2,3,0,1],
+// then the half-row and row mirrors, which meet lanes holding the same partial
+// sums as lane ^ 4 and lane ^ 8), so the additions are those of the butterfly.
+__device__ inline double row16_sum(double v) {
+  v += dpp_row<0xB1>(v);
+  v += dpp_row<0x4E>(v);
+  v += dpp_row<0x141>(v);
+  v += dpp_row<0x140>(v);
+  return v;
+}
+
 // ordering of LDS accesses inside one wave (no workgroup barrier needed)
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1224,7 +1246,7 @@ __device__ inline void eval_runs(const Tab& T, const int* runs, const double* va
 // the first NV fields (v and sigma: degree <= p - 1; the steps past nkv[I]
 // would only add exact zeros).  Each lane then
 // weights its four results (points l/16 + 4r, entry 16 I + l%16) by L_a and
-// the 16 lanes of a row are summed: every lane of row l/16 ends with val[c][r]
+// the 16 lanes of a row are summed (DPP): every lane of row l/16 ends with val[c][r]
 // of point l/16 + 4r.  PWW: powers of the wave's 16 points, PWW[(pt*4 + v)*P1
 // + e] = var_v^e (v = 0: th).
 template <int NC, int NV>
@@ -1291,9 +1313,7 @@ __device__ inline void eval16_mfma(const double* CMd, int nA16, int ldb, int nl,
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) val[c][r] += __shfl_xor(val[c][r], off, 64);
+    for (int r = 0; r < 4; ++r) val[c][r] = row16_sum(val[c][r]);
 }
 
 // eval16_mfma at two times per point: every point has 5 power rows (P1 each:
@@ -1370,15 +1390,11 @@ __device__ inline void eval16_mfma2(const double* CMd, int nA16, int ldb, int nl
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) valt[c][r] += __shfl_xor(valt[c][r], off, 64);
+    for (int r = 0; r < 4; ++r) valt[c][r] = row16_sum(valt[c][r]);
 #pragma unroll
   for (int c = 0; c < NB; ++c)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) valb[c][r] += __shfl_xor(valb[c][r], off, 64);
+    for (int r = 0; r < 4; ++r) valb[c][r] = row16_sum(valb[c][r]);
 }
 
 // Dense coefficients CM_c[a][b] of the fields of group r's solution xs (3+1D):
