@@ -48,13 +48,15 @@ def _normal_up(P):
 
 
 def global_solve(coords, elems, c, tents, p, q, v0, sig0, alpha=0.5, beta=0.5, gD=None, gN=None, bface_kind=None,
-                 U0=None, recover="off"):
+                 U0=None, recover="off", seed="monomial", info=None):
     """Solve eq. 2.5 for all tents at once.  v0 (ne,Q), sig0 (ne,Q,n) are the
     initial values at the element quadrature points (U0 too with a recovery).
     bface_kind: 0 Dirichlet / 1 Neumann per boundary facet in the order of
     Topology.boundary_facets() (None: all Dirichlet).  Returns the final (v,
     sigma) at the element quadrature points at t = T, the solution vector and
-    (with a recovery) the final U there."""
+    (with a recovery) the final U there.  seed: spatial seed basis of the
+    Trefftz recursion (Sec. 3, Sec. 6.3).  info (a dict, optional) receives
+    the assembled sparse matrix under "A"."""
     topo = Topology(coords, elems, c)
     n = topo.n
     lam, wref = simplex_rule(n, q)
@@ -86,7 +88,7 @@ def global_solve(coords, elems, c, tents, p, q, v0, sig0, alpha=0.5, beta=0.5, g
         for r, cr in enumerate(cvals):
             h = max(np.sqrt(((a[0] - b[0]) ** 2).sum() + cr * cr * (a[1] - b[1]) ** 2)
                     for a, b in itertools.combinations(pts, 2))
-            groups[cr] = (Group(n, p, cr, X[V].copy(), 0.5 * (tb + tt), h), offset)
+            groups[cr] = (Group(n, p, cr, X[V].copy(), 0.5 * (tb + tt), h, seed), offset)
             offset += NB
         emap = {e: groups[float(topo.c[e])] for e in P}
         # time-like faces of this tent (vertical; built from the pre-tent front)
@@ -211,6 +213,8 @@ def global_solve(coords, elems, c, tents, p, q, v0, sig0, alpha=0.5, beta=0.5, g
                              + np.einsum("q,qi,qj->ij", dS * beta * sa * sb_, Sb_ @ nrm, Sa @ nrm))
                         add(ob + c0, oa + c0, M)
     A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(ndof, ndof))
+    if info is not None:
+        info["A"] = A
     sol = spla.spsolve(A.tocsc(), rhs)
     # final values at the element points from the last tent over each element
     vT = np.zeros((topo.ne, len(wref)))

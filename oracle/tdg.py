@@ -63,7 +63,7 @@ import numpy as np
 
 from .quadrature import simplex_rule
 from .topology import Topology
-from .trefftz import dim_U, first_order_fields, trefftz_basis
+from .trefftz import SEED_KINDS, dim_U, first_order_fields, trefftz_basis
 
 
 def _monomials(n: int, deg: int):
@@ -78,13 +78,14 @@ def _monomials(n: int, deg: int):
 
 
 @lru_cache(maxsize=None)
-def _coef_mats(n: int, p: int):
-    """Dense coefficient matrices of the basis over the monomials of degree <= p:
-    returns (mono, Cv, Cs, CU) with Cv (M, NW), Cs (n, M, NW), CU (M, NW)."""
+def _coef_mats(n: int, p: int, seed: str = "monomial"):
+    """Dense coefficient matrices of the basis (seeded by `seed`, Sec. 6.3)
+    over the monomials of degree <= p: returns (mono, Cv, Cs, CU) with Cv (M,
+    NW), Cs (n, M, NW), CU (M, NW)."""
     mono = _monomials(n, p)
     idx = {m: i for i, m in enumerate(mono)}
-    fo = first_order_fields(n, p)
-    basis = trefftz_basis(n, p)
+    fo = first_order_fields(n, p, seed)
+    basis = trefftz_basis(n, p, seed)
     NW = len(fo)
     M = len(mono)
     Cv = np.zeros((M, NW))
@@ -106,13 +107,14 @@ def _coef_mats(n: int, p: int):
 class Group:
     """Scaled Trefftz basis of one wave-speed group of a tent (Remark 3.1)."""
 
-    def __init__(self, n, p, c, xK, tK, hK):
+    def __init__(self, n, p, c, xK, tK, hK, seed="monomial"):
         self.n, self.p, self.c, self.xK, self.tK, self.hK = n, p, c, xK, tK, hK
+        self.seed = seed
 
     def fields(self, x, t):
         """Basis fields at physical points x (Q, n), t (Q,):
         returns v (Q, NW), sigma (Q, NW, n), U (Q, NW)."""
-        kexp, aexp, Cv, Cs, CU = _coef_mats(self.n, self.p)
+        kexp, aexp, Cv, Cs, CU = _coef_mats(self.n, self.p, self.seed)
         xh = (x - self.xK) / self.hK
         th = self.c * (t - self.tK) / self.hK
         mono = th[:, None] ** kexp[None, :]
@@ -126,8 +128,11 @@ class Group:
 
 class OracleTDG:
     def __init__(self, coords, elems, c, tents, layer_ptr, p: int, q: int,
-                 alpha: float = 0.5, beta: float = 0.5, gD=None, gN=None, bface_kind=None, recover="mean"):
+                 alpha: float = 0.5, beta: float = 0.5, gD=None, gN=None, bface_kind=None, recover="mean",
+                 seed: str = "monomial"):
         self.topo = Topology(coords, elems, c)
+        assert seed in SEED_KINDS
+        self.seed = seed  # spatial seed basis of the Trefftz recursion (Sec. 3, Sec. 6.3)
         self.n = self.topo.n
         self.tents = list(tents)
         self.layer_ptr = list(layer_ptr)
@@ -211,7 +216,7 @@ class OracleTDG:
             h = 0.0
             for (xa, ta), (xb, tb_) in itertools.combinations(pts, 2):
                 h = max(h, np.sqrt(((xa - xb) ** 2).sum() + cr * cr * (ta - tb_) ** 2))
-            groups.append(Group(n, p, cr, xK, tK, h))
+            groups.append(Group(n, p, cr, xK, tK, h, self.seed))
 
         A = np.zeros((m * NW, m * NW))
         rhs = np.zeros(m * NW)
