@@ -112,6 +112,13 @@ typedef struct {
                            (quadrature Gram only: trefftz_set_gram_mode(1) and precision = 1
                            are rejected);
                         0: off; other values: TDG_EINVAL */
+  int32_t seed_basis;/* spatial basis that seeds the recursion of eq. 3.1 at t = t_K (Sec. 3;
+                        the three choices compared in Sec. 6.3), in the scaled coordinates of
+                        Remark 3.1: 0 = monomials x^beta (the default; the best conditioned),
+                        1 = products of Legendre polynomials P_(beta_m)(x_m), 2 = products of
+                        Chebyshev polynomials T_(beta_m)(x_m); all span the same U^p, so the
+                        solution differs by round-off only, as far as the conditioning of the
+                        tent systems allows.  Other values: TDG_EINVAL */
 } tdg_opts;
 
 enum {

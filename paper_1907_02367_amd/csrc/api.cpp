@@ -9,6 +9,7 @@
 #include <stdexcept>
 
 #include "tdg_internal.h"
+#include "trefftz_table.h"
 
 namespace tdg {
 
@@ -397,6 +398,8 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   if (opts->precision != 0 && opts->precision != 1) return fail(TDG_EINVAL, "precision must be 0 or 1");
   if (!(opts->alpha > 0) || !(opts->beta > 0)) return fail(TDG_EINVAL, "alpha and beta must be positive");
   if (opts->recover_U < 0 || opts->recover_U > 2) return fail(TDG_EINVAL, "recover_U must be 0, 1 or 2");
+  if (opts->seed_basis < 0 || opts->seed_basis > 2)
+    return fail(TDG_EINVAL, "seed_basis must be 0 (monomials), 1 (Legendre) or 2 (Chebyshev)");
   if (opts->recover_U == 2 && opts->precision != 0)
     return fail(TDG_EINVAL, "recover_U = 2 (the recovery terms for every test function) needs precision = 0");
   auto X = new tdg_ctx();
@@ -413,7 +416,7 @@ int trefftz_create(const tdg_mesh* mesh, const double* c, const tdg_tents* tents
   const int q = opts->q ? opts->q : opts->p_max;
   X->quad = simplex_rule(n, q);
   X->tabs.resize(opts->p_max + 1);
-  for (int p = 1; p <= opts->p_max; ++p) X->tabs[p] = build_table(n, p);
+  for (int p = 1; p <= opts->p_max; ++p) X->tabs[p] = build_table(n, p, opts->seed_basis);
   X->nq = (int64_t)X->topo.ne * X->quad.Q;
   // speed groups per patch
   for (int v = 0; v < X->topo.nv; ++v) {
@@ -1195,6 +1198,31 @@ int tdg_debug_eval_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t* e
   for (int i = 0; i < 8; ++i) info[14 + i] = t.ev_nkv[i];
   if (ev_ab) std::copy(t.ev_ab.begin(), t.ev_ab.end(), ev_ab);
   if (ev_ex) std::copy(t.ev_ex.begin(), t.ev_ex.end(), ev_ex);
+  return TDG_OK;
+}
+
+// Internal (host-side table checks in the tests): the field and U tables of
+// degree p as built.  info[5] = {M, NW, n, nnz of the field rows, nnz of the U
+// rows}; expo[M (n+1)] the exponents (t first) of the monomials, fo_ptr[NW (n+1)
+// + 1] / fo_idx / fo_coef the rows (function j, component v, sigma_1..n) and
+// u_ptr[NW + 1] / u_idx / u_coef those of U_j.  Arrays are nullable.
+int tdg_debug_field_tables(const tdg_ctx* X, int32_t p, int32_t* info, int32_t* expo, int32_t* fo_ptr,
+                           int32_t* fo_idx, double* fo_coef, int32_t* u_ptr, int32_t* u_idx, double* u_coef) {
+  if (!X || !info) return fail(TDG_EINVAL, "NULL argument");
+  if (p < 1 || p > X->opts.p_max) return fail(TDG_EINVAL, "p out of range");
+  const Table& t = X->tabs[p];
+  info[0] = t.M;
+  info[1] = t.NW;
+  info[2] = X->topo.n;
+  info[3] = (int32_t)t.fo_idx.size();
+  info[4] = (int32_t)t.u_idx.size();
+  if (expo) std::copy(t.expo.begin(), t.expo.end(), expo);
+  if (fo_ptr) std::copy(t.fo_ptr.begin(), t.fo_ptr.end(), fo_ptr);
+  if (fo_idx) std::copy(t.fo_idx.begin(), t.fo_idx.end(), fo_idx);
+  if (fo_coef) std::copy(t.fo_coef.begin(), t.fo_coef.end(), fo_coef);
+  if (u_ptr) std::copy(t.u_ptr.begin(), t.u_ptr.end(), u_ptr);
+  if (u_idx) std::copy(t.u_idx.begin(), t.u_idx.end(), u_idx);
+  if (u_coef) std::copy(t.u_coef.begin(), t.u_coef.end(), u_coef);
   return TDG_OK;
 }
 

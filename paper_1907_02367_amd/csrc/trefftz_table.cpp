@@ -3,8 +3,13 @@
 // U(x,t) = sum_{k+|alpha|<=p} a_{k,alpha} x^alpha t^k solves -Lap U + U_tt = 0
 // (c = 1) iff for k >= 2
 //   a_{k,alpha} = 1/(k(k-1)) sum_m (alpha_m+1)(alpha_m+2) a_{k-2,alpha+2e_m}   (eq. 3.1)
-// seeded by monomials: U(.,0) = x^beta, U_t(.,0) = 0 for |beta| <= p, then
-// U(.,0) = 0, U_t(.,0) = x^beta for |beta| <= p-1 (dim = C(p+n,n) + C(p-1+n,n)).
+// seeded by a basis of the spatial polynomials: U(.,0) = b_beta, U_t(.,0) = 0
+// for |beta| <= p, then U(.,0) = 0, U_t(.,0) = b_beta for |beta| <= p-1
+// (dim = C(p+n,n) + C(p-1+n,n)).  b_beta is the monomial x^beta (seed 0), or
+// the product over the variables of Legendre polynomials P_(beta_m)(x_m)
+// (seed 1) or Chebyshev polynomials T_(beta_m)(x_m) (seed 2), the three
+// choices of Sec. 6.3; the recursion is linear in the seed, so a seeded
+// function is the same combination of the monomial-seeded ones.
 // Any c is reached by the change of variables of Remark 3.1, applied in the
 // kernels.  Coefficients are computed in exact 64-bit rationals (they stay
 // far below 2^53 for p <= 10) and rounded once to double.
@@ -19,7 +24,7 @@
 #include <numeric>
 #include <stdexcept>
 
-#include "tdg_internal.h"
+#include "trefftz_table.h"
 
 namespace tdg {
 
@@ -41,6 +46,10 @@ struct Rat {
     }
     if (num == 0) den = 1;
   }
+  static int64_t fit(__int128 v) {
+    if (v > (__int128)INT64_MAX || v < -(__int128)INT64_MAX) throw std::overflow_error("Trefftz table coefficient overflow");
+    return (int64_t)v;
+  }
   Rat operator+(const Rat& o) const {
     __int128 n = (__int128)num * o.den + (__int128)o.num * den;
     __int128 d = (__int128)den * o.den;
@@ -55,13 +64,20 @@ struct Rat {
       d /= a;
     }
     Rat r;
-    r.num = (int64_t)n;
-    r.den = (int64_t)d;
+    r.num = fit(n);
+    r.den = fit(d);
     r.norm();
     return r;
   }
-  Rat mul(int64_t k) const { return Rat((int64_t)((__int128)num * k), den); }
-  Rat div(int64_t k) const { return Rat(num, (int64_t)((__int128)den * k)); }
+  Rat mul(int64_t k) const { return Rat(fit((__int128)num * k), den); }
+  Rat div(int64_t k) const { return Rat(num, fit((__int128)den * k)); }
+  Rat mul(const Rat& o) const {
+    // cross-reduce first so the products stay small
+    const int64_t g1 = std::gcd(num < 0 ? -num : num, o.den), g2 = std::gcd(o.num < 0 ? -o.num : o.num, den);
+    const int64_t a = g1 ? num / g1 : num, b = g2 ? o.num / g2 : o.num;
+    const int64_t c = g2 ? den / g2 : den, d = g1 ? o.den / g1 : o.den;
+    return Rat(fit((__int128)a * b), fit((__int128)c * d));
+  }
   double to_double() const { return (double)num / (double)den; }
   bool zero() const { return num == 0; }
 };
@@ -90,9 +106,41 @@ std::vector<Key> multi(int n, int deg) {
   return out;
 }
 
+// Coefficients c_0..c_d of the degree-d seed polynomial of one variable, from
+// the closed forms (Sec. 6.3 names the families):
+//   Legendre  P_d(x) = 2^-d sum_k (-1)^k C(d,k) C(2d-2k,d) x^(d-2k),
+//   Chebyshev T_d(x) = sum_k (-1)^k d 2^(d-2k-1) (d-k-1)! / (k! (d-2k)!) x^(d-2k)  (d >= 1).
+std::vector<Rat> seed_1d(int kind, int d) {
+  std::vector<Rat> c((size_t)d + 1, Rat(0));
+  auto binom = [](int a, int b) {
+    int64_t r = 1;
+    for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+    return r;
+  };
+  auto fact = [](int a) {
+    int64_t r = 1;
+    for (int i = 2; i <= a; ++i) r *= i;
+    return r;
+  };
+  if (kind == 0 || d == 0) {
+    c[(size_t)d] = Rat(1);
+    return c;
+  }
+  for (int k = 0; 2 * k <= d; ++k) {
+    const int64_t sg = (k & 1) ? -1 : 1;
+    if (kind == 1)
+      c[(size_t)(d - 2 * k)] = Rat(sg * binom(d, k) * binom(2 * d - 2 * k, d), (int64_t)1 << d);
+    else
+      c[(size_t)(d - 2 * k)] =
+          Rat(sg * d * fact(d - k - 1), fact(k) * fact(d - 2 * k)).mul((int64_t)1 << (d - 2 * k)).div(2);
+  }
+  return c;
+}
+
 }  // namespace
 
-Table build_table(int n, int p) {
+Table build_table(int n, int p, int seed) {
+  if (seed < 0 || seed > 2) throw std::invalid_argument("seed basis must be 0, 1 or 2");
   Table T;
   T.n = n;
   T.p = p;
@@ -160,6 +208,35 @@ Table build_table(int n, int p) {
           }
         }
     basis.push_back(a);
+  }
+  if (seed != 0) {
+    // b_beta = sum_gamma prod_m s_(beta_m)[gamma_m] x^gamma: combine the
+    // monomial-seeded functions of the same type with those weights
+    std::map<std::pair<int, Key>, int> pos;
+    for (size_t i = 0; i < seeds.size(); ++i) pos[seeds[i]] = (int)i;
+    std::vector<std::map<Key, Rat>> comb(seeds.size());
+    for (size_t i = 0; i < seeds.size(); ++i) {
+      const Key b = seeds[i].second;
+      std::vector<std::vector<Rat>> s1(n);
+      for (int m = 0; m < n; ++m) s1[m] = seed_1d(seed, b[1 + m]);
+      Key g{0, 0, 0, 0};
+      // every gamma with gamma_m <= beta_m
+      for (;;) {
+        Rat w(1);
+        for (int m = 0; m < n; ++m) w = w.mul(s1[m][(size_t)g[1 + m]]);
+        if (!w.zero())
+          for (auto& kv : basis[(size_t)pos.at({seeds[i].first, g})]) {
+            Rat& dst = comb[i][kv.first];
+            dst = dst + kv.second.mul(w);
+          }
+        int m = 0;
+        while (m < n && g[1 + m] == b[1 + m]) g[1 + m++] = 0;
+        if (m == n) break;
+        g[1 + m]++;
+      }
+      for (auto it = comb[i].begin(); it != comb[i].end();) it = it->second.zero() ? comb[i].erase(it) : std::next(it);
+    }
+    basis.swap(comb);
   }
   const int N = (int)basis.size();
   T.NW = N - 1;
@@ -394,5 +471,7 @@ Table build_table(int n, int p) {
   }
   return T;
 }
+
+Table build_table(int n, int p) { return build_table(n, p, 0); }
 
 }  // namespace tdg

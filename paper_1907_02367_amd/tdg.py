@@ -39,7 +39,7 @@ class _Mesh(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("p_max", ctypes.c_int32), ("q", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("precision", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("recover_U", ctypes.c_int32)]
+                ("recover_U", ctypes.c_int32), ("seed_basis", ctypes.c_int32)]
 
 
 _lib = None
@@ -278,14 +278,15 @@ class Trefftz:
 
     def __init__(self, coords, elems, c, tents: Tents, p_max: int, q: int = 0, alpha: float = 0.5,
                  beta: float = 0.5, precision: int = 0, recover_U: int = 1, device=None, bind: bool = True,
-                 bface_kind=None):
+                 bface_kind=None, seed_basis: int = 0):
         self.n = int(np.asarray(coords).shape[1])
         self.nv = int(np.asarray(coords).shape[0])
         self.ne = int(np.asarray(elems).shape[0])
         self.tents = tents
         m, keep = _mesh(coords, elems, bface_kind)
         c = np.ascontiguousarray(c, dtype=np.float64)
-        opts = _Opts(int(p_max), int(q), float(alpha), float(beta), int(precision), 1, int(recover_U))
+        opts = _Opts(int(p_max), int(q), float(alpha), float(beta), int(precision), 1, int(recover_U),
+                     int(seed_basis))
         h = ctypes.c_void_p()
         _check(lib().trefftz_create(ctypes.byref(m), _ptr(c), tents._h, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

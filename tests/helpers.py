@@ -6,23 +6,26 @@ from oracle.pitcher import pitch
 from oracle.tdg import OracleTDG
 
 
-def oracle_for(pr, field=None, p=None, q=None):
+SEEDS = ("monomial", "legendre", "chebyshev")  # seed_basis 0, 1, 2
+
+
+def oracle_for(pr, field=None, p=None, q=None, seed_basis=0):
     f = field or pr.data
     tents, lp = pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
     o = OracleTDG(pr.coords, pr.elems, pr.c, tents, lp, p=p or pr.p, q=q or pr.qpts,
-                  alpha=pr.alpha, beta=pr.beta, gD=lambda x, t: f.v(x, t))
+                  alpha=pr.alpha, beta=pr.beta, gD=lambda x, t: f.v(x, t), seed=SEEDS[seed_basis])
     X = o.quad_points()
     o.set_initial(f.v(X, 0.0), f.sigma(X, 0.0), f.U(X, 0.0))
     return o
 
 
-def gpu_for(pr, field=None, p_max=None, q=None, precision=0, gram_mode=0):
+def gpu_for(pr, field=None, p_max=None, q=None, precision=0, gram_mode=0, seed_basis=0):
     from paper_1907_02367_amd import tdg
 
     f = field or pr.data
     T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
     ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max or pr.p, q=q or pr.qpts,
-                      alpha=pr.alpha, beta=pr.beta, precision=precision)
+                      alpha=pr.alpha, beta=pr.beta, precision=precision, seed_basis=seed_basis)
     if gram_mode:
         ctx.set_gram_mode(gram_mode)
     xq, w = ctx.quad_points()

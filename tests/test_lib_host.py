@@ -127,6 +127,11 @@ def test_errors_are_reported_not_raised_across_the_abi():
     with pytest.raises(tdg.TdgError) as ei:
         ctx2.set_gram_mode(1)
     assert ei.value.name == "TDG_EINVAL"
+    # seed basis of the recursion: 0, 1 or 2 only
+    for sb in (-1, 3):
+        with pytest.raises(tdg.TdgError) as ei:
+            tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=3, seed_basis=sb, bind=False)
+        assert ei.value.name == "TDG_EINVAL"
     # boundary-facet kinds must be 0 or 1
     nbf = len(tdg.boundary_facets(pr.coords, pr.elems))
     bad = np.zeros(nbf, np.int8)
