@@ -58,7 +58,7 @@ CASES = {
 }
 
 
-def _run_both(name, recover, gram_mode):
+def _run_both(name, recover, gram_mode, seed_basis=0):
     from paper_1907_02367_amd import tdg
 
     pr, f, rule = CASES[name]()
@@ -73,14 +73,14 @@ def _run_both(name, recover, gram_mode):
     tents, lp = pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
     o = OracleTDG(pr.coords, pr.elems, pr.c, tents, lp, p=pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta,
                   gD=lambda x, t: f.v(x, t), gN=_gN(f, pr.n), bface_kind=kinds,
-                  recover={1: "mean", 2: "all"}[recover])
+                  recover={1: "mean", 2: "all"}[recover], seed=("monomial", "legendre", "chebyshev")[seed_basis])
     X = o.quad_points()
     o.set_initial(f.v(X, 0.0), f.sigma(X, 0.0), f.U(X, 0.0))
     o.run()
     T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
     assert T.as_list() == tents
     ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=pr.p, q=pr.qpts, alpha=pr.alpha, beta=pr.beta,
-                      recover_U=recover, bface_kind=kinds)
+                      recover_U=recover, bface_kind=kinds, seed_basis=seed_basis)
     if gram_mode:
         ctx.set_gram_mode(gram_mode)
     xq, _ = ctx.quad_points()
@@ -130,3 +130,24 @@ def test_paper_recovery_matches_oracle(name):
         assert abs(eg[0] - eo[0]) <= d + 1e-13 * ref, (eg, eo, d)
         if "poly" in name:
             assert eg[1] < 1e-10, eg
+
+
+@pytest.mark.parametrize("recover,gram_mode", [(1, 0), (1, 1), (2, 0)],
+                         ids=["mean_row_quadrature_gram", "mean_row_moment_gram", "paper_recovery"])
+@pytest.mark.parametrize("seed_basis", [1, 2], ids=["legendre", "chebyshev"])
+@pytest.mark.parametrize("name", ["1d_p5_standing", "2d_p3_poly", "2d_p3_two_speeds", "3d_p3_standing"])
+def test_seeded_bases_with_neumann_faces_and_recoveries(name, seed_basis, recover, gram_mode):
+    # Legendre and Chebyshev seeds (Sec. 6.3) through the Neumann faces, the
+    # speed interfaces and both recoveries of U; polynomial data of degree p
+    # is reproduced whatever the seed (the space is the same)
+    say(f"[gpu next1] seed {seed_basis} {name}, recover_U {recover}, gram mode {gram_mode}")
+    pr, f, o, ctx, xq, (v, s, U) = _run_both(name, recover, gram_mode, seed_basis)
+    r_vs = rel_l2(np.concatenate([v.ravel(), s.ravel()]), np.concatenate([o.v.ravel(), o.sig.ravel()]))
+    r_U = rel_l2(U, o.U)
+    m_vs = elem_max_rel(np.concatenate([v[..., None], s], -1), np.concatenate([o.v[..., None], o.sig], -1))
+    m_U = elem_max_rel(U, o.U)
+    say(f"  rel diff (v, sigma) {r_vs:.2e}, U {r_U:.2e}, per element {m_vs:.2e}, {m_U:.2e}")
+    assert r_vs <= TOL and r_U <= TOL and m_vs <= 10 * TOL and m_U <= 10 * TOL, (r_vs, r_U, m_vs, m_U)
+    if "poly" in name:
+        ea, er = ctx.eval_error(f.v(xq, pr.T), f.sigma(xq, pr.T))
+        assert er < 1e-10, er

@@ -10,8 +10,6 @@ functions, an independent route), the invariance of the discrete solution
 under a change of basis of the same space, and the paper's finding of
 Sec. 6.3 on the 1+1D standing wave of Sec. 6."""
 from fractions import Fraction as Fr
-import itertools
-import math
 
 import numpy as np
 import pytest
@@ -148,6 +146,38 @@ def test_solution_does_not_depend_on_the_seed_basis(dim):
             o = _tent_run(pr, f, seed, rec)
             for a, b in ((o.v, ref.v), (o.sig, ref.sig), (o.U, ref.U)):
                 assert np.abs(a - b).max() <= 1e-11 * max(1.0, np.abs(b).max())
+
+
+def test_seed_invariance_with_interfaces_neumann_faces_and_the_paper_recovery():
+    # two speeds (interface faces of Sec. 4.2), Neumann faces on y = 1 (eq. 4.1)
+    # and the recovery of U with every test function (Sec. 5)
+    from oracle.topology import Topology
+
+    pr = C.cfg4_interface_2d(m=9, p=3)
+    pr.T = 0.3
+    f = pr.data
+    topo = Topology(pr.coords, pr.elems, pr.c)
+    kinds = []
+    for e, k in topo.boundary_facets():
+        cen = pr.coords[[v for j, v in enumerate(pr.elems[e]) if j != k]].mean(axis=0)
+        kinds.append(1 if cen[1] > 1 - 1e-9 else 0)
+    assert 0 < sum(kinds) < len(kinds)
+
+    def gN(x, t):
+        return np.where(np.abs(x[:, 1] - 1.0) < 1e-12, f.sigma(x, t)[:, 1], 0.0)
+
+    tents, lp = pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    out = []
+    for seed in SEED_KINDS:
+        o = OracleTDG(pr.coords, pr.elems, pr.c, tents, lp, p=pr.p, q=pr.p, gD=lambda x, t: f.v(x, t), gN=gN,
+                      bface_kind=kinds, recover="all", seed=seed)
+        X = o.quad_points()
+        o.set_initial(f.v(X, 0.0), f.sigma(X, 0.0), f.U(X, 0.0))
+        o.run()
+        out.append((o.v, o.sig, o.U))
+    for got in out[1:]:
+        for a, b in zip(got, out[0]):
+            assert np.abs(a - b).max() <= 1e-11 * max(1.0, np.abs(b).max())
 
 
 def _global_1d(p, seed, ne=8):
