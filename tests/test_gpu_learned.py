@@ -359,3 +359,57 @@ def test_trained_network_gains_over_fixed_pmax():
     assert e_fixed <= 1e-6 and e_learned <= 1e-6 and e_vs_fixed <= 1e-6
     assert dof_learned <= 0.9 * dof_fixed
     assert t_learned < 0.9 * t_fixed
+
+
+def test_training_loop_steps_match_oracle_and_fit_a_teacher():
+    """DegreeNet.train end to end on the GPU (full batch, so deterministic):
+    each of two single steps against the oracle's gradient and Adam step from
+    the GPU's own state (the second with the step counter carried over, so the
+    bias correction is that of step 2), then 400 steps on the outputs of a
+    teacher of the same architecture must cut the oracle's own loss at the
+    trained BF16 weights tenfold (the oracle's run of the same loop: 0.84 to
+    0.017).  Compared are the updates of the weights whose gradient is at
+    least 1e-2 of the largest: the kernels' gradient is accurate to 1e-4 of
+    the largest entry, so to 1 % there, and each update must be within 2 % of
+    the oracle's (a wrong learning rate or bias correction is off by a factor
+    of two or more); elsewhere FP32 rounding may flip the sign of a tiny
+    gradient, and the first Adam step moves every weight by at most lr."""
+    from paper_1907_02367_amd.learned_p import DegreeNet
+
+    torch = _torch()
+    n = 2048
+    rng = np.random.default_rng(21)
+    x = rng.normal(0, 1.0, (n, 8)).astype(np.float32)
+    tw = np.random.default_rng(22).normal(0, 0.2, OM.N_PARAM).astype(np.float32)
+    t, _ = OM.forward(OM.bf16_value(OM.bf16_bits(tw)), x.astype(np.float64))
+    t = t.astype(np.float32)
+    mask = (rng.uniform(size=(n, 7)) < 0.8).astype(np.float32)
+    X, Y, Mk = (torch.from_numpy(a).cuda() for a in (x, t, mask))
+    x64, t64, m64 = x.astype(np.float64), t.astype(np.float64), mask.astype(np.float64)
+    f32 = lambda a: float(np.float32(a))  # noqa: E731
+    net = DegreeNet(seed=3)
+    say("[mlp train] two single steps against the oracle")
+    for step, lr in ((1, 3e-3), (2, 1e-3)):
+        w_before = net.w32.cpu().numpy().astype(np.float64)
+        m_before = net.m.cpu().numpy().astype(np.float64)
+        v_before = net.v.cpu().numpy().astype(np.float64)
+        bits = net.wb.cpu().numpy().view(np.uint16)
+        assert np.array_equal(bits, OM.bf16_bits(w_before.astype(np.float32)))
+        net.train(X, Y, Mk, steps=1, lr=lr, lr_end=lr)
+        assert net.step == step
+        go, _ = OM.backward(OM.bf16_value(bits), x64, t64, m64, float(mask.size))
+        wo, _, _ = OM.adam_step(w_before, go, m_before, v_before, step, f32(lr), f32(0.9), f32(0.999), f32(1e-8))
+        w_gpu = net.w32.cpu().numpy().astype(np.float64)
+        big = np.abs(go) >= 1e-2 * np.abs(go).max()
+        assert big.sum() > 1000
+        du = np.abs((w_gpu - w_before) - (wo - w_before))
+        assert (du <= 2e-2 * np.abs(wo - w_before) + 1e-6 * np.abs(w_before).max())[big].all()
+        if step == 1:
+            assert np.abs(w_gpu - w_before).max() <= lr * (1 + 1e-5) + 1e-7 * np.abs(w_before).max()
+    L0 = OM.loss(OM.bf16_value(OM.bf16_bits(w_gpu.astype(np.float32))), x64, t64, m64, float(mask.size))
+    say(f"[mlp train] 400 steps from loss {L0:.3e}")
+    hist = net.train(X, Y, Mk, steps=400, lr=3e-3, lr_end=3e-4, log_every=100)
+    bits = net.wb.cpu().numpy().view(np.uint16)
+    L1 = OM.loss(OM.bf16_value(bits), x64, t64, m64, float(mask.size))
+    say(f"  loss {L0:.3e} -> {L1:.3e} (oracle at the trained weights); GPU history {hist}")
+    assert np.isfinite(L1) and L1 <= 0.1 * L0, (L0, L1)
