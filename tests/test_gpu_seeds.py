@@ -18,10 +18,13 @@ TOL = 1e-10
 # effect Sec. 6.3 reports): under a random one-ulp relative perturbation of
 # every tent matrix and right-hand side the oracle's own result moves by at
 # most 4e-14 (1D p = 6), 6e-14 (2D p = 4), 5e-13 (3D p = 3), but at 3D p = 5 by
-# 2.5e-10 (Legendre) and 1.1e-9 (Chebyshev) against 2.4e-13 with monomials
-# (three perturbations each).  As for the other ill-conditioned cases the
-# tolerance is 50x the largest floor where that exceeds the default.
-TOL_CASE = {("3d_p5_b", 1): 1.2e-8, ("3d_p5_b", 2): 5.3e-8}
+# 2.5e-10 (Legendre) and 1.1e-9 (Chebyshev) against 2.4e-13 with monomials,
+# at 2D p = 6 by 3.2e-12 and 5.1e-12 (5.7e-13), and at the largest degree, 1D
+# p = 10, by 4.4e-11 and 5.4e-11 (5.6e-11) (three perturbations each).  As for
+# the other ill-conditioned cases the tolerance is 50x the largest floor where
+# that exceeds the default (1D p = 10: 3e-9, the monomial case's).
+TOL_CASE = {("3d_p5_b", 1): 1.2e-8, ("3d_p5_b", 2): 5.3e-8, ("2d_p6_m6", 1): 1.6e-10, ("2d_p6_m6", 2): 2.5e-10,
+            ("1d_p10", 1): 3e-9, ("1d_p10", 2): 3e-9}
 
 
 def say(*a):
@@ -31,6 +34,8 @@ def say(*a):
 
 def _case(name):
     pr = {"1d_p6": lambda: C.cfg1_standing_1d(n_elems=16, p=6),
+          "1d_p10": lambda: C.cfg1_standing_1d(n_elems=8, p=10),
+          "2d_p6_m6": lambda: C.cfg2_plane_2d(m=6, p=6),
           "2d_p4_m6": lambda: C.cfg2_plane_2d(m=6, p=4),
           "3d_p3_b": lambda: C.cfg5_cube_3d(m=2, p=3, variant="b"),
           "3d_p5_b": lambda: C.cfg5_cube_3d(m=2, p=5, variant="b")}[name]()
@@ -49,7 +54,7 @@ def _gpu_state(pr, seed_basis, gram_mode):
 
 @pytest.mark.parametrize("gram_mode", [0, 1], ids=["quadrature_gram", "moment_gram"])
 @pytest.mark.parametrize("seed_basis", [1, 2], ids=["legendre", "chebyshev"])
-@pytest.mark.parametrize("name", ["1d_p6", "2d_p4_m6", "3d_p3_b", "3d_p5_b"])
+@pytest.mark.parametrize("name", ["1d_p6", "1d_p10", "2d_p4_m6", "2d_p6_m6", "3d_p3_b", "3d_p5_b"])
 def test_seeded_run_matches_oracle(name, seed_basis, gram_mode):
     pr = _case(name)
     say(f"[gpu seeds] {name} seed {seed_basis} gram mode {gram_mode}: n={pr.n} p={pr.p} ne={len(pr.elems)}")
