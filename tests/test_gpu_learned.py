@@ -238,16 +238,18 @@ def test_adaptive_sweep_matches_oracle_with_same_degrees():
     assert r_vs <= 1e-10 and r_U <= 1e-10
 
 
-def test_adaptive_3d_one_pass_matches_fixed_degree_solve():
+@pytest.mark.parametrize("seed_basis", [0, 1, 2], ids=["monomial", "legendre", "chebyshev"])
+def test_adaptive_3d_one_pass_matches_fixed_degree_solve(seed_basis):
     """3+1D degree-adaptive sweep in moment mode: below p_max the indicator and
     the tent's top values come from one pass of the matrix-core evaluation
     (kept in the workgroup's global slot until the tent is accepted).  A plain
     solve at the recorded degrees (write-back only, no indicator) must leave
-    the same stored values bit for bit."""
+    the same stored values bit for bit, with each seed basis of the Trefftz
+    recursion (Sec. 6.3)."""
     torch = _torch()
     pr = C.cfg5_cube_3d(m=3, p=5, variant="b", regions=1, T=0.2)
     pr.gamma = 0.4 * 0.8 ** 4  # (the jittered cube needs the lower edge slope to pitch)
-    ctx, xq, w = gpu_for(pr, gram_mode=1)
+    ctx, xq, w = gpu_for(pr, gram_mode=1, seed_basis=seed_basis)
     nt = ctx.tents.n_tents
     # a network that reads the patch size: degrees 3..5 (weights exact in BF16)
     d = OM.unpack(np.zeros(OM.N_PARAM))
@@ -268,7 +270,7 @@ def test_adaptive_3d_one_pass_matches_fixed_degree_solve():
     ps, pu = p_sel.cpu().numpy(), p_used.cpu().numpy()
     say(f"  3D selected degrees {np.bincount(ps, minlength=6)[2:]}, used {np.bincount(pu, minlength=6)[2:]}")
     assert (pu < pr.p).sum() > 0 and len(set(pu.tolist())) >= 2
-    ref, _, _ = gpu_for(pr, gram_mode=1)
+    ref, _, _ = gpu_for(pr, gram_mode=1, seed_basis=seed_basis)
     ref.layer_solve(p_per_tent=p_used)
     ref.status()
     for a, b in zip(ctx.read_state(), ref.read_state()):

@@ -80,3 +80,24 @@ def test_seed_basis_leaves_the_gpu_solution_unchanged(name):
         got = _gpu_state(pr, sb, 0)
         for a, b in zip(got, ref):
             assert rel_l2(a, b) <= TOL, (sb, rel_l2(a, b))
+
+
+@pytest.mark.parametrize("seed_basis", [1, 2], ids=["legendre", "chebyshev"])
+def test_seeded_mixed_precision_matches_oracle(seed_basis):
+    """The FP32 matrix-core Gram with FP64 refinement (or the per-tent FP64
+    fallback) with a seeded basis reaches the FP64 bar against the oracle."""
+    pr = _case("2d_p4_m6")
+    say(f"[gpu seeds] mixed precision, seed {seed_basis}")
+    o = oracle_for(pr, seed_basis=seed_basis)
+    o.run()
+    ctx, xq, w = gpu_for(pr, precision=1, seed_basis=seed_basis)
+    ctx.layer_solve()
+    v, s, U = ctx.read_state()
+    ctx.status()
+    ir, _ = ctx.tent_stats()
+    r_vs = rel_l2(np.concatenate([v.ravel(), s.ravel()]), np.concatenate([o.v.ravel(), o.sig.ravel()]))
+    r_U = rel_l2(U, o.U)
+    say(f"  rel diff (v, sigma) {r_vs:.2e}, U {r_U:.2e}; refinement steps mean {(ir % 1000).mean():.2f}, "
+        f"FP64 fallback {100 * (ir >= 1000).mean():.1f} %")
+    assert ((ir % 1000) >= 1).all()
+    assert r_vs <= TOL and r_U <= TOL, (r_vs, r_U)
