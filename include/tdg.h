@@ -98,7 +98,8 @@ void tent_free(tdg_tents* tents);
 
 /* ---- solver context ------------------------------------------------------------ */
 typedef struct {
-  int32_t p_max;     /* highest degree of U^p used by any tent, 1..10 */
+  int32_t p_max;     /* highest degree of U^p used by any tent, 1..10; in 3+1D at most 9 (at
+                        p = 10 a tent's working set does not fit in LDS: TDG_EINVAL) */
   int32_t q;         /* Gauss points per direction of the simplex rule; 0 -> p_max (exact to 2q-1) */
   double alpha;      /* penalty on Dirichlet and interface faces (Sec. 2.4), e.g. 0.5 */
   double beta;       /* interface penalty (Sec. 2.4), e.g. 0.5 */

@@ -198,3 +198,20 @@ def test_gram_modes_and_shapes_are_planned_on_the_host():
         with pytest.raises(tdg.TdgError) as ei:
             mixed.set_gram_mode(1)
         assert ei.value.name == "TDG_EINVAL"
+
+
+def test_largest_degree_per_dimension():
+    # the tables exist up to p = 10 in every dimension; in 3+1D the working
+    # set of a tent at p = 10 exceeds the LDS of a compute unit, which create
+    # reports instead of failing at launch
+    from paper_1907_02367_amd import tdg
+
+    pr = C.cfg5_cube_3d(m=1, variant="b")
+    T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, 0.05, 0.16)
+    tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=9, bind=False)
+    with pytest.raises(tdg.TdgError) as ei:
+        tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=10, bind=False)
+    assert ei.value.name == "TDG_EINVAL" and "LDS" in str(ei.value)
+    for pr in (C.cfg1_standing_1d(n_elems=4), C.cfg2_plane_2d(m=3)):
+        T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, 0.05, 0.16)
+        tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=10, bind=False)
