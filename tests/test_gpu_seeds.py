@@ -101,3 +101,21 @@ def test_seeded_mixed_precision_matches_oracle(seed_basis):
         f"FP64 fallback {100 * (ir >= 1000).mean():.1f} %")
     assert ((ir % 1000) >= 1).all()
     assert r_vs <= TOL and r_U <= TOL, (r_vs, r_U)
+
+
+def test_seed_study_errors_agree_at_low_degree():
+    """The Sec. 6.3 study on the library (studies/seeds.py): on the 1+1D
+    standing wave the error at T is the same for the three seeds up to p = 7
+    (same space, well-conditioned systems): the errors differ by at most the
+    distance of the solutions (reverse triangle inequality), round-off of a
+    solution of norm about 1, so by 1e-11 at most; every run at the largest
+    degree stays accurate (error below 1e-9)."""
+    from paper_1907_02367_amd.studies import seeds as S
+
+    for p in (2, 4, 7, 10):
+        errs = [S.run(8, p, sb)[1] for sb in range(3)]
+        say(f"[gpu seeds] study p={p}: " + ", ".join(f"{e:.3e}" for e in errs))
+        if p <= 7:
+            assert max(abs(e - errs[0]) for e in errs) <= 1e-11, errs
+        else:
+            assert all(np.isfinite(e) and e < 1e-9 for e in errs), errs
