@@ -41,7 +41,7 @@ def _lib_tables(ctx, p):
 
 
 @pytest.mark.parametrize("dim,p_max,degrees", [("1d", 10, range(1, 11)), ("2d", 10, (1, 2, 3, 4, 5, 6, 10)),
-                                                ("3d", 8, (1, 2, 3, 4, 8))])
+                                                ("3d", 9, (1, 2, 3, 4, 8, 9))])
 def test_library_tables_equal_the_oracle_for_every_seed(dim, p_max, degrees):
     from paper_1907_02367_amd import tdg
 
