@@ -472,6 +472,7 @@ Table build_table(int n, int p, int seed) {
   return T;
 }
 
+// The monomial-seeded tables, the library's default basis.
 Table build_table(int n, int p) { return build_table(n, p, 0); }
 
 }  // namespace tdg
