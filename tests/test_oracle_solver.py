@@ -205,3 +205,32 @@ def test_parity_tolerance_is_fifty_times_the_one_ulp_floor(name, builder, tol, m
         floors.append(rel_l2(np.concatenate([o2.v.ravel(), o2.sig.ravel()]), ref))
     assert max(floors) > 0
     assert tol / 3 <= 50 * max(floors) <= tol * 1.5, (name, floors)
+
+
+@pytest.mark.parametrize("case", ["2d", "2d_two_speeds"])
+def test_order_inside_a_layer_is_free(case):
+    # the tents of a layer sit at pairwise non-adjacent vertices, so their
+    # patches share no element and no vertex (any two vertices of a simplex
+    # are joined by an edge): solving a layer's tents in any order gives the
+    # same state bit for bit (Sec. 2.2: independent tents in parallel)
+    pr = C.cfg2_plane_2d(m=6, p=3) if case == "2d" else C.cfg4_interface_2d(m=9, p=3)
+    pr.T = 0.4
+    f = pr.data
+    tents, lp = pitch(pr.coords, pr.elems, pr.c, pr.T, pr.gamma)
+    rng = np.random.default_rng(11)
+    runs = []
+    for shuffle in (False, True):
+        o = OracleTDG(pr.coords, pr.elems, pr.c, tents, lp, p=pr.p, q=pr.p, gD=lambda x, t: f.v(x, t))
+        X = o.quad_points()
+        o.set_initial(f.v(X, 0.0), f.sigma(X, 0.0), f.U(X, 0.0))
+        for l in range(len(lp) - 1):
+            idx = np.arange(lp[l], lp[l + 1])
+            if shuffle:
+                rng.shuffle(idx)
+            for i in idx:
+                V, tb, tt = tents[i]
+                o.solve_tent(V, tb, tt)
+        runs.append((o.v.copy(), o.sig.copy(), o.U.copy(), o.tau.copy()))
+    assert any(lp[l + 1] - lp[l] > 2 for l in range(len(lp) - 1))  # some layer is really reordered
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
