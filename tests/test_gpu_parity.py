@@ -53,6 +53,9 @@ CASES = {
     "3d_p2_e_per_element_speeds": lambda: (C.cfg5_cube_3d(m=2, p=2, variant="e", T=0.15), None, None),
     "3d_p3_e_per_element_speeds": lambda: (C.cfg5_cube_3d(m=2, p=3, variant="e", T=0.15), None, None),
     "3d_p8_b_multipass_gram": lambda: (C.cfg5_cube_3d(m=2, p=8, variant="b"), None, None),
+    # the coarse 6^3 cube (1,296 tetrahedra) in full, speeds drawn per region
+    # (125 regions: tents with up to eight speed groups at region corners)
+    "3d_p3_a_cube6_regions": lambda: (C.cfg5_cube_3d(m=6, p=3, variant="a", regions=5), None, None),
     # the largest degree with tables (p = 10)
     "1d_p10_max_degree": lambda: (C.cfg1_standing_1d(n_elems=8, p=10), None, None),
     "2d_p10_max_degree": lambda: (C.cfg2_plane_2d(m=3, p=10, T=0.2), None, None),
