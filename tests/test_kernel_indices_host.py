@@ -90,13 +90,15 @@ def _degree_blocks(D):
     return lst, [sum(lst[16 * i]) for i in range(nb)]
 
 
+@pytest.mark.parametrize("seed_basis", [0, 2], ids=["monomial_seeds", "chebyshev_seeds"])
 @pytest.mark.parametrize("p_max", [8, 5])
-def test_moment_phase_indices_stay_in_bounds_3d(p_max):
+def test_moment_phase_indices_stay_in_bounds_3d(p_max, seed_basis):
+    # (a seeded basis has about twice the table terms, which moves the LDS plan)
     from paper_1907_02367_amd import tdg
 
     pr = C.cfg5_cube_3d(m=3, p=p_max, variant="b", regions=1)
     T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, 0.05, 0.4 * 0.8 ** 4)
-    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max, bind=False)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max, bind=False, seed_basis=seed_basis)
     ctx.set_gram_mode(1)
     n = 3
     checked_tiles = 0
@@ -171,8 +173,9 @@ def test_moment_phase_indices_stay_in_bounds_3d(p_max):
 
 
 @pytest.mark.parametrize("gram_mode", [0, 1])
+@pytest.mark.parametrize("seed_basis", [0, 2], ids=["monomial_seeds", "chebyshev_seeds"])
 @pytest.mark.parametrize("p_max", [8, 3])
-def test_matrix_core_evaluation_indices_3d(p_max, gram_mode):
+def test_matrix_core_evaluation_indices_3d(p_max, gram_mode, seed_basis):
     """The matrix-core evaluation of the solution at points (indicator and
     write-back, 3+1D): every monomial of degree <= p is one (L, R) pair of the
     two-variable list, each pair at most once; the k-steps of tile I cover the
@@ -185,7 +188,7 @@ def test_matrix_core_evaluation_indices_3d(p_max, gram_mode):
 
     pr = C.cfg5_cube_3d(m=3, p=p_max, variant="b", regions=1)
     T = tdg.tent_pitch(pr.coords, pr.elems, pr.c, 0.05, 0.4 * 0.8 ** 4)
-    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max, bind=False)
+    ctx = tdg.Trefftz(pr.coords, pr.elems, pr.c, T, p_max=p_max, bind=False, seed_basis=seed_basis)
     ctx.set_gram_mode(gram_mode)
     L = tdg.lib()
     f = L.tdg_debug_eval_tables
