@@ -119,7 +119,9 @@ typedef struct {
                         1 = products of Legendre polynomials P_(beta_m)(x_m), 2 = products of
                         Chebyshev polynomials T_(beta_m)(x_m); all span the same U^p, so the
                         solution differs by round-off only, as far as the conditioning of the
-                        tent systems allows.  Other values: TDG_EINVAL */
+                        tent systems allows: the seeded bases are worse conditioned, and at
+                        3+1D p = 8 Chebyshev-seeded tent systems are singular to working
+                        precision (condition numbers up to 1.7e20).  Other values: TDG_EINVAL */
 } tdg_opts;
 
 enum {
